@@ -1,0 +1,28 @@
+"""Build the oracle's shared library (test infrastructure only).
+
+The oracle is plain C99 compiled with gcc -O2 and no fast-math or FP
+contraction, so every FP64 operation is a single correctly rounded IEEE
+operation.  Run ``python -m oracle.build`` or call :func:`build`.
+"""
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCES = ["healpix.c", "trace.c", "merge.c", "chem.c"]
+LIB = os.path.join(HERE, "liboracle.so")
+
+
+def build(verbose: bool = False) -> str:
+    cmd = ["gcc", "-std=c99", "-D_GNU_SOURCE", "-O2", "-fPIC", "-shared",
+           "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wno-unused-function",
+           "-pthread", "-o", LIB + ".tmp"]
+    cmd += [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))
