@@ -1,0 +1,160 @@
+"""Benchmark of the ray-tracing sweep on one MI355X.
+
+A step is one full trace pass (nrt_trace_step: spawn, march, deposit,
+split, terminate, until no ray is left) over the workload's sources, with
+the grid, ionization field and source table already resident in HBM.  The
+default workload is the 128^3 lognormal field with 64 sources.  Both
+arithmetic paths are timed.  `value` is the mixed path's segments/s; the
+FP64 path is reported beside it.
+
+Prints one JSON line with the metric, the roofline of the march kernel
+(algorithmic bytes per launch over the average launch duration, from HIP
+events on the library's stream) and the oracle timed on the host cores on a
+bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ray-segments/sec + ms per RT step, FP32-mixed vs FP64, % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per segment: absorber of the cell and of its neighbour,
+# read-modify-write of Gamma in both (FP64: 8+8+16+16; mixed: FP32 absorber
+# words, FP64 Gamma accumulators: 4+4+16+16)
+BYTES_PER_SEGMENT = {"fp64": 48.0, "mixed": 40.0}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    import workloads as W
+    if name == "lognormal-128-64src":
+        return W.config2()
+    if name == "stromgren-testA-32":
+        return W.config1()
+    if name == "lognormal-256-4096src-bubbles":
+        return W.config3()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def run_path(nrt, w, precision, steps, warmup, capacity):
+    import torch
+    desc = nrt.make_desc(w.n, w.h_cm, periodic=w.periodic, n_min_ray=w.n_min_ray, l_max=w.l_max,
+                         tau_max=w.tau_max, n_th=w.n_th, precision=precision)
+    ctx = nrt.init_grid(desc, w.n_H, w.x, device="cuda:0", max_sources=len(w.ndot),
+                        ray_capacity=capacity)
+    ctx.add_sources(w.pos, w.ndot)
+    gamma = torch.empty((w.n,) * 3, dtype=torch.float64, device="cuda:0")
+    for _ in range(warmup):
+        _, b = ctx.trace_step(gamma)
+    torch.cuda.synchronize()
+    segs, kernel_ms, launches = 0, 0.0, 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, b = ctx.trace_step(gamma)
+        avg, nl = ctx.last_kernel_time()
+        kernel_ms += avg * nl
+        launches += nl
+        segs += b["segments"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.destroy()
+    return dict(wall_s=wall, ms_per_step=1e3 * wall / steps, segments_per_step=segs // steps,
+                segments_per_s=segs / wall, kernel_ms_total=kernel_ms, launches=launches,
+                avg_launch_ms=kernel_ms / max(launches, 1), budget=b)
+
+
+def roofline(path, res):
+    """Per launch: the algorithmic bytes of the segments one march launch
+    processes over the launch's duration (HIP events on the library's
+    stream); averaged over the timed launches this is bytes per segment times
+    segments over the summed launch time."""
+    achieved = BYTES_PER_SEGMENT[path] * res["segments_per_s_kernel"] / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_march", "bytes_per_segment": BYTES_PER_SEGMENT[path],
+            "avg_launch_ms": round(res["avg_launch_ms"], 4), "launches": res["launches"]}
+
+
+def cpu_baseline(w, sources, threads):
+    import oracle
+    import workloads as W
+    s = W.subset(w, sources)
+    p = oracle.make_params(w.n, w.h_cm, periodic=w.periodic, n_min_ray=w.n_min_ray,
+                           l_max=w.l_max, tau_max=w.tau_max, n_th=w.n_th)
+    t0 = time.perf_counter()
+    _, b = oracle.trace(p, s.n_H, s.x, s.pos, s.ndot, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": round(b["segments"] / dt, 1), "unit": "ray-segments/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{len(s.ndot)} of {len(w.ndot)} sources (seeded subset) of {w.name}, "
+                      f"full grid, FP64, {b['segments']} segments in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="lognormal-128-64src")
+    ap.add_argument("--capacity", type=int, default=1 << 23)
+    ap.add_argument("--paths", default="mixed,fp64")
+    ap.add_argument("--cpu-sources", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path "
+              f"(--gpus {args.gpus} requested)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2512_12466_amd as nrt
+    nrt.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = make_workload(args.workload)
+    res = {}
+    for path in args.paths.split(","):
+        prec = nrt.MIXED if path == "mixed" else nrt.FP64
+        r = run_path(nrt, w, prec, args.steps, args.warmup, args.capacity)
+        r["segments_per_s_kernel"] = r["segments_per_step"] * args.steps / (
+            r["kernel_ms_total"] / 1e3)
+        res[path] = r
+        log(f"[{path}] {r['ms_per_step']:.2f} ms/step, {r['segments_per_step']} segments, "
+            f"{r['segments_per_s'] / 1e9:.3f} Gseg/s wall, "
+            f"{r['segments_per_s_kernel'] / 1e9:.3f} Gseg/s in march kernels "
+            f"({r['launches'] // args.steps} launches/step)")
+    head = "mixed" if "mixed" in res else next(iter(res))
+    h = res[head]
+    out = {
+        "metric": METRIC, "value": round(h["segments_per_s"], 1), "unit": "ray-segments/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(h["ms_per_step"], 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if head == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "sources": int(len(w.ndot)),
+                   "periodic": bool(w.periodic), "n_min_ray": w.n_min_ray, "l_max": w.l_max,
+                   "tau_max": w.tau_max, "path": head, "decisions": "f64"},
+        "roofline": roofline(head, h),
+    }
+    for path, r in res.items():
+        if path == head:
+            continue
+        out[f"{path}_path"] = {"value": round(r["segments_per_s"], 1), "unit": "ray-segments/s",
+                               "ms_per_step": round(r["ms_per_step"], 3),
+                               "dtype": "f64" if path == "fp64" else "f32",
+                               "roofline": roofline(path, r)}
+    if not args.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sources, threads)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,207 @@
+/*
+ * nyxrt -- MI355X-native adaptive ray-tracing sweep of Nyx-RT (arXiv 2512.12466).
+ *
+ * C ABI: plain pointers and sizes, no C++ types, no exceptions.  Every call
+ * returns an nrt_status; on failure nrt_last_error() holds a message and no
+ * caller buffer has been written (except where a function says otherwise).
+ *
+ * Conventions
+ *   Grid       cubic, n cells per side, cell width h_cm.  Fields are flat
+ *              arrays of n^3 cell-centred values indexed c = i + n*(j + n*k)
+ *              (i fastest; a C-ordered [k][j][i] array).
+ *   Positions  in cell units: cell (i,j,k) covers [i,i+1)x[j,j+1)x[k,k+1).
+ *   x          the IONIZED fraction; the absorber is a_abs = (1 - x) n_H
+ *              (Sec. "Geometric correction").
+ *   Gamma      photo-ionisation rate per neutral H atom [s^-1] (Eq. lut_eqn).
+ *   Device     pointers marked "device" are HIP device memory of the device
+ *              that was current at nrt_init_grid; pointers marked "host" are
+ *              ordinary host memory.
+ *   Streams    all device work of a context is enqueued on the stream given
+ *              at nrt_init_grid.  Calls that return host results synchronise
+ *              that stream before returning.
+ *   Ownership  the caller owns every buffer it passes, including the device
+ *              workspace; the library allocates no device memory.  Inputs are
+ *              copied at call time and may be freed after the call returns.
+ *   Threads    a context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef NYXRT_H
+#define NYXRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nrt_ctx nrt_ctx;
+
+typedef enum {
+  NRT_OK = 0,
+  NRT_ERR_ARG = 1,      /* invalid argument or input value                      */
+  NRT_ERR_STATE = 2,    /* call not valid in the context's state                */
+  NRT_ERR_NOMEM = 3,    /* workspace (or host memory) too small                 */
+  NRT_ERR_OVERFLOW = 4, /* a ray queue or source table would overflow           */
+  NRT_ERR_DEVICE = 5,   /* a HIP call failed                                    */
+  NRT_ERR_INTERNAL = 6  /* invariant violated inside the library                */
+} nrt_status;
+
+/* Arithmetic of the march (a3-a4).  Both paths take every discrete decision
+   (cell crossing, split, face choice, thresholds) in FP64 with the same
+   operations, so they execute the same segments; NRT_MIXED computes the
+   absorber, optical depth, attenuation and deposits in FP32 and keeps the
+   photon budget in FP64. */
+typedef enum { NRT_FP64 = 0, NRT_MIXED = 1 } nrt_precision;
+
+/* Overlap correction (Sec. "Geometric correction"). */
+typedef enum {
+  NRT_CORR_NONE = 0,         /* f_c = 1                                             */
+  NRT_CORR_LINEAR = 1,       /* Eq. correction, no neighbour deposit                */
+  NRT_CORR_CONSERVATIVE = 2, /* Eqs. new_correction + new_secondary (the paper's)   */
+  NRT_CORR_SQUARED = 3,      /* f_c = (1/2 + D_edge/L_pix)^2, no neighbour deposit  */
+  NRT_CORR_NAIVE = 4         /* Eq. correction; Eq. secondary_correction dropped
+                                where n'_H < n_th ("naive thresholding")           */
+} nrt_corr;
+
+#define NRT_MAX_LEVEL 14 /* HEALPix level cap: 12 * 4^14 pixels fit in 32 bits */
+
+typedef struct {
+  int32_t n;          /* cells per side, 1 <= n <= 4096                            */
+  double h_cm;        /* cell width [cm], > 0                                      */
+  int32_t periodic;   /* 1: rays wrap and stop after sqrt(3) n cells (Sec.
+                         "Periodic BCs"); 0: rays leaving the box escape           */
+  double sigma0;      /* cross-section at the threshold [cm^2], >= 0              */
+  double n_min_ray;   /* N_min^ray of Eq. split_criterion, >= 0; 0 never splits   */
+  int32_t l_max;      /* HEALPix level cap, 0 .. NRT_MAX_LEVEL                    */
+  double tau_max;     /* optical-depth cap, > 0                                   */
+  double n_th;        /* neighbour density threshold [cm^-3] (Eq. new_correction) */
+  int32_t corr;       /* nrt_corr                                                 */
+  int32_t precision;  /* nrt_precision                                            */
+} nrt_grid_desc;
+
+/* Source-merging parameters (Sec. "Source Merging Algorithm"). */
+typedef struct {
+  double dr;           /* shell step [cells], > 0                       */
+  double x_th;         /* a sample is ionized iff x >= x_th             */
+  double f_req;        /* a shell passes iff N_ion / N_tot >= f_req     */
+  int32_t n_min;       /* below n_min samples every sample must pass    */
+  double r_max;        /* radius cap [cells]                            */
+  double f_ov;         /* overlap factor                                */
+  double eps;          /* squared-distance tolerance [cells^2]          */
+  int32_t shell_level; /* HEALPix level of the shell directions, 0..6   */
+} nrt_merge_params;
+
+/* Photon budget of one pass: emitted = absorbed + escaped + truncated. */
+typedef struct {
+  double emitted;    /* sum of source rates [photons/s]                         */
+  double absorbed;   /* deposited on the grid                                   */
+  double escaped;    /* left the box, or reached sqrt(3) n in a periodic box    */
+  double truncated;  /* dropped at tau_max, or at l_max when a split was due    */
+  uint64_t segments; /* cell segments marched (the throughput unit)             */
+  uint64_t rays;     /* rays marched: spawned plus split children               */
+  uint64_t splits;   /* rays that split into four                               */
+  uint64_t rays_per_level[NRT_MAX_LEVEL + 1];
+} nrt_budget;
+
+/* Bytes of device workspace a context needs: fields for n^3 cells, a table
+   of max_sources sources, and ray queues of ray_capacity slots per HEALPix
+   level (ray_capacity >= 4096; larger queues mean fewer, larger launches).
+   Returns NRT_ERR_ARG for an invalid descriptor. */
+nrt_status nrt_workspace_bytes(const nrt_grid_desc* desc, int64_t max_sources,
+                               int64_t ray_capacity, size_t* bytes);
+
+/* Create a context on the current HIP device.  n_H and x_ion: device, n^3
+   FP64 each, read during the call (n_H finite and >= 0, 0 <= x_ion <= 1,
+   else NRT_ERR_ARG).  workspace: device, ws_bytes >= nrt_workspace_bytes(),
+   256-byte aligned, owned by the caller and used until nrt_destroy.
+   hip_stream: a hipStream_t (NULL = the null stream).  *out receives the
+   context; nothing is created on failure. */
+nrt_status nrt_init_grid(nrt_ctx** out, const nrt_grid_desc* desc, const double* n_H,
+                         const double* x_ion, int64_t max_sources, int64_t ray_capacity,
+                         void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* Replace the ionized fraction (device, n^3 FP64, 0 <= x <= 1). */
+nrt_status nrt_set_ionization(nrt_ctx* ctx, const double* x_ion);
+
+/* Copy the context's ionized fraction into x_out (device, n^3 FP64). */
+nrt_status nrt_get_ionization(nrt_ctx* ctx, double* x_out);
+
+/* Append m point sources (Sec. "Halo finding and source luminosity"):
+   pos host m*3 in cell units, each in [0, n); ndot host m rates
+   [photons/s], finite and >= 0.  A source casts 12 HEALPix level-0 rays
+   from its position, each with rate ndot / 12.  NRT_ERR_OVERFLOW if the
+   table would exceed max_sources (nothing appended). */
+nrt_status nrt_add_sources(nrt_ctx* ctx, int64_t m, const double* pos, const double* ndot);
+
+/* Remove every source. */
+nrt_status nrt_clear_sources(nrt_ctx* ctx);
+
+/* Number of sources in the table. */
+nrt_status nrt_source_count(const nrt_ctx* ctx, int64_t* m);
+
+/* Copy the source table to the host: pos m*3, ndot m, radius m (bubble
+   radius from the last merge, else 0); any pointer may be NULL. */
+nrt_status nrt_get_sources(nrt_ctx* ctx, double* pos, double* ndot, double* radius);
+
+/* Source merging (Sec. "Source Merging Algorithm", Alg. source_merge) on the
+   GPU, using the context's ionized fraction: snap sources to cells and merge
+   same-cell sources, compute each source's bubble radius (max_radius), unite
+   sources whose bubbles overlap, collapse each group into one source at the
+   member cell nearest its flux-weighted centroid, sort lexicographically by
+   (i,j,k).  The table is replaced by the merged catalogue, whose positions
+   are cell centres; *m_after receives its size. */
+nrt_status nrt_merge_sources(nrt_ctx* ctx, const nrt_merge_params* mp, int64_t* m_after);
+
+/* One ray-tracing pass (Alg. trace_rays): spawn 12 rays per source, march
+   cell by cell accumulating optical depth and depositing Gamma (Eq. lut_eqn
+   with V_box = h^3, the overlap correction of desc->corr), split by Eq.
+   split_criterion into the 4 nested HEALPix children, terminate at tau_max,
+   at l_max, at box exit or after sqrt(3) n cells when periodic, until no ray
+   is left.  gamma_out: device n^3 FP64, overwritten.  budget: host, filled
+   on return (the call synchronises).  NRT_ERR_OVERFLOW if the ray queues
+   cannot hold a split (Gamma then unspecified). */
+nrt_status nrt_trace_step(nrt_ctx* ctx, double* gamma_out, nrt_budget* budget);
+
+/* One radiation step of length dt_s (Secs. "Time integration" and
+   "Iterative nonlinear solve"): iterate { trace with a = (1 - x_avg) n_H;
+   update x by the time-averaged solution of Eq. chem_ode with C_H = 0 and
+   recombination coefficient alpha = clumping * alpha_B } until the largest
+   change of x_avg is below tol or max_iter passes, then commit x(dt).
+   gamma_out: device n^3 FP64 (Gamma of the last pass); budget: host (last
+   pass); iters: host, passes done.  The context's x is updated. */
+nrt_status nrt_rt_step(nrt_ctx* ctx, double dt_s, double alpha, double tol, int32_t max_iter,
+                       double* gamma_out, nrt_budget* budget, int32_t* iters);
+
+/* Test hook: march k injected rays that never split (desc->n_min_ray must be
+   0): origin host k*3 (cell units, inside the box), dir host k*3 unit
+   vectors, level host k (sets the pixel solid angle of the overlap
+   correction), L host k rates.  gamma_out: device n^3 FP64, overwritten. */
+nrt_status nrt_trace_rays_debug(nrt_ctx* ctx, int64_t k, const double* origin, const double* dir,
+                                const int32_t* level, const double* L, double* gamma_out,
+                                nrt_budget* budget);
+
+/* HEALPix nested pixel-centre directions computed by the device code:
+   out host 3*count doubles for pixels first .. first+count-1 of `level`.
+   Used to check the device pixelisation. */
+nrt_status nrt_healpix_dirs(nrt_ctx* ctx, int32_t level, int64_t first, int64_t count,
+                            double* out);
+
+/* Average duration [ms] of the march kernel launches of the last
+   nrt_trace_step, timed with HIP events on the context's stream, and the
+   number of those launches. */
+nrt_status nrt_last_kernel_time(const nrt_ctx* ctx, double* march_ms, int32_t* launches);
+
+/* Destroy a context (the workspace remains the caller's).  NULL is a no-op. */
+nrt_status nrt_destroy(nrt_ctx* ctx);
+
+/* Static description of a status code. */
+const char* nrt_status_str(nrt_status s);
+
+/* Message of the last failure of ctx (or of the last failed nrt_init_grid
+   when ctx is NULL); valid until the next call on the same context. */
+const char* nrt_last_error(const nrt_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NYXRT_H */

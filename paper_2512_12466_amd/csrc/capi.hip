@@ -1,0 +1,603 @@
+// C ABI of the nyxrt library (include/nyxrt.h): argument checking, the
+// workspace plan, and the host orchestration of the trace (level queues
+// processed depth-first in chunks that always fit the next level's queue).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+using nrt::Accum;
+using nrt::Layout;
+using nrt::MarchArgs;
+using nrt::RayQueue;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+nrt_status fail(nrt_ctx* c, nrt_status s, const std::string& msg) {
+  if (c)
+    c->err = msg;
+  else
+    g_init_error = msg;
+  return s;
+}
+
+nrt_status hip_fail(nrt_ctx* c, hipError_t e, const char* what) {
+  return fail(c, NRT_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_OR_FAIL(ctx, expr)                               \
+  do {                                                       \
+    hipError_t e_ = (expr);                                  \
+    if (e_ != hipSuccess) return hip_fail((ctx), e_, #expr); \
+  } while (0)
+
+bool check_desc(const nrt_grid_desc* d, std::string& why) {
+  if (!d) return why = "desc is NULL", false;
+  if (d->n < 1 || d->n > 4096) return why = "n must be in [1, 4096]", false;
+  if (!(d->h_cm > 0.0) || !std::isfinite(d->h_cm)) return why = "h_cm must be > 0", false;
+  if (!(d->sigma0 >= 0.0) || !std::isfinite(d->sigma0)) return why = "sigma0 must be >= 0", false;
+  if (!(d->n_min_ray >= 0.0) || !std::isfinite(d->n_min_ray))
+    return why = "n_min_ray must be >= 0", false;
+  if (d->l_max < 0 || d->l_max > NRT_MAX_LEVEL) return why = "l_max out of range", false;
+  if (!(d->tau_max > 0.0)) return why = "tau_max must be > 0", false;
+  if (std::isnan(d->n_th)) return why = "n_th is NaN", false;
+  if (d->corr < NRT_CORR_NONE || d->corr > NRT_CORR_NAIVE) return why = "bad corr", false;
+  if (d->precision != NRT_FP64 && d->precision != NRT_MIXED) return why = "bad precision", false;
+  if (d->periodic != 0 && d->periodic != 1) return why = "periodic must be 0 or 1", false;
+  return true;
+}
+
+// Omega(l) = 4 pi / (12 4^l) (Eq. split_criterion); split iff s^2 > 1/(N_min Omega(l))
+void level_constants(nrt_ctx* c) {
+  for (int l = 0; l <= nrt::kMaxLevel; ++l) {
+    const double omega = (4.0 * M_PI) / (12.0 * std::ldexp(1.0, 2 * l));
+    c->sqrt_omega[l] = std::sqrt(omega);
+    c->r2split[l] = c->desc.n_min_ray > 0.0 ? 1.0 / (c->desc.n_min_ray * omega) : INFINITY;
+  }
+}
+
+nrt_status sync_read_accum(nrt_ctx* c) {
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->h_acc, c->acc, sizeof(Accum), hipMemcpyDeviceToHost,
+                                c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return NRT_OK;
+}
+
+nrt_status read_u64(nrt_ctx* c, const unsigned long long* dev, unsigned long long* out) {
+  HIP_OR_FAIL(c, hipMemcpyAsync(&c->h_acc->out_count[0], dev, sizeof(unsigned long long),
+                                hipMemcpyDeviceToHost, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  *out = c->h_acc->out_count[0];
+  return NRT_OK;
+}
+
+nrt_status upload_sources(nrt_ctx* c) {
+  if (!c->sources_dirty) return NRT_OK;
+  const size_t m = c->h_ndot.size();
+  if (m) {
+    std::vector<double> l0(m);
+    for (size_t k = 0; k < m; ++k) l0[k] = c->h_ndot[k] / 12.0;
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->src_pos, c->h_pos.data(), m * 3 * sizeof(double),
+                                  hipMemcpyHostToDevice, c->stream));
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->src_l0, l0.data(), m * sizeof(double),
+                                  hipMemcpyHostToDevice, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  }
+  c->sources_dirty = false;
+  return NRT_OK;
+}
+
+MarchArgs base_args(const nrt_ctx* c, double* gamma) {
+  MarchArgs a;
+  std::memset(&a, 0, sizeof(a));
+  const nrt_grid_desc& d = c->desc;
+  a.n = d.n;
+  a.periodic = d.periodic;
+  a.corr = d.corr;
+  a.l_max = d.l_max;
+  a.h_cm = d.h_cm;
+  a.sigma0 = d.sigma0;
+  a.tau_max = d.tau_max;
+  a.s_max = d.periodic ? std::sqrt(3.0) * double(d.n) : INFINITY;
+  a.h3 = d.h_cm * d.h_cm * d.h_cm;
+  a.t_min = std::exp(-d.tau_max);
+  a.kf = float(d.sigma0 * d.h_cm);
+  a.a64 = c->a64;
+  a.a32 = c->a32;
+  a.gamma = gamma;
+  a.src_pos = c->src_pos;
+  a.src_l0 = c->src_l0;
+  for (int l = 0; l <= nrt::kMaxLevel; ++l) a.sqrt_omega_tab[l] = c->sqrt_omega[l];
+  a.acc = c->acc;
+  return a;
+}
+
+struct PassState {
+  nrt_budget* b;
+  double* gamma;
+};
+
+nrt_status launch_timed(nrt_ctx* c, const MarchArgs& a, int64_t rays) {
+  const size_t k = size_t(c->launches) * 2;
+  while (c->ev.size() < k + 2) {
+    hipEvent_t e;
+    HIP_OR_FAIL(c, hipEventCreate(&e));
+    c->ev.push_back(e);
+  }
+  HIP_OR_FAIL(c, hipEventRecord(c->ev[k], c->stream));
+  HIP_OR_FAIL(c, nrt::launch_march(c, a, rays));
+  HIP_OR_FAIL(c, hipEventRecord(c->ev[k + 1], c->stream));
+  c->launches += 1;
+  return NRT_OK;
+}
+
+// March rays [begin, end) of `level` (virtual spawn indices when spawn),
+// then, depth first, every level below them.  Chunks hold at most a quarter
+// of the queue capacity, so the children of a chunk always fit.
+nrt_status process_level(nrt_ctx* c, PassState& ps, int level, bool spawn, int64_t begin,
+                         int64_t end) {
+  const int64_t cap = c->lay.capacity;
+  const int64_t chunk = std::max<int64_t>(1, cap / 4);
+  const bool last = level >= c->desc.l_max;
+  for (int64_t b = begin; b < end; b += chunk) {
+    const int64_t e = std::min(end, b + chunk);
+    MarchArgs a = base_args(c, ps.gamma);
+    a.level = level;
+    a.spawn = spawn ? 1 : 0;
+    a.src_begin = 0;
+    a.begin = b;
+    a.end = e;
+    a.in = c->queue[level];
+    a.r2split = c->r2split[level];
+    a.sqrt_omega = c->sqrt_omega[level];
+    unsigned long long* cnt = &c->acc->out_count[level + 1];
+    if (!last) {
+      a.out = c->queue[level + 1];
+      a.out_cap = cap;
+      HIP_OR_FAIL(c, hipMemsetAsync(cnt, 0, sizeof(unsigned long long), c->stream));
+    } else {
+      a.out = c->queue[level];
+      a.out_cap = 0;
+    }
+    nrt_status st = launch_timed(c, a, e - b);
+    if (st) return st;
+    ps.b->rays_per_level[level] += uint64_t(e - b);
+    ps.b->rays += uint64_t(e - b);
+    if (!last) {
+      unsigned long long k = 0;
+      st = read_u64(c, cnt, &k);
+      if (st) return st;
+      if (int64_t(k) > cap)
+        return fail(c, NRT_ERR_OVERFLOW, "ray queue overflow at level " + std::to_string(level + 1));
+      ps.b->splits += k / 4;
+      if (k > 0) {
+        st = process_level(c, ps, level + 1, false, 0, int64_t(k));
+        if (st) return st;
+      }
+    }
+  }
+  return NRT_OK;
+}
+
+nrt_status finish_timing(nrt_ctx* c) {
+  double total = 0.0;
+  for (int q = 0; q < c->launches; ++q) {
+    float ms = 0.0f;
+    HIP_OR_FAIL(c, hipEventElapsedTime(&ms, c->ev[2 * q], c->ev[2 * q + 1]));
+    total += ms;
+  }
+  c->march_ms = total;
+  return NRT_OK;
+}
+
+// One trace pass over the current absorber field into gamma.
+nrt_status trace_pass(nrt_ctx* c, double* gamma, nrt_budget* out) {
+  nrt_status st = upload_sources(c);
+  if (st) return st;
+  nrt_budget b;
+  std::memset(&b, 0, sizeof(b));
+  for (double v : c->h_ndot) b.emitted += v;
+  HIP_OR_FAIL(c, nrt::launch_zero(gamma, c->lay.cells, c->cu_count, c->stream));
+  HIP_OR_FAIL(c, nrt::launch_zero_accum(c->acc, c->stream));
+  c->launches = 0;
+  c->march_ms = 0.0;
+  PassState ps{&b, gamma};
+  const int64_t m = int64_t(c->h_ndot.size());
+  if (m > 0) {
+    st = process_level(c, ps, 0, true, 0, 12 * m);
+    if (st) return st;
+  }
+  st = sync_read_accum(c);
+  if (st) return st;
+  st = finish_timing(c);
+  if (st) return st;
+  const Accum& h = *c->h_acc;
+  if (h.overflow) return fail(c, NRT_ERR_OVERFLOW, "ray queue overflow");
+  b.absorbed = h.absorbed;
+  b.escaped = h.escaped;
+  b.truncated = h.truncated;
+  b.segments = h.segments;
+  if (out) *out = b;
+  return NRT_OK;
+}
+
+nrt_status prep_absorber(nrt_ctx* c, const double* x_field) {
+  const double* keep = c->x;
+  c->x = const_cast<double*>(x_field);
+  HIP_OR_FAIL(c, nrt::launch_zero_accum(c->acc, c->stream));
+  hipError_t e = nrt::launch_prep(c);
+  c->x = const_cast<double*>(keep);
+  if (e != hipSuccess) return hip_fail(c, e, "launch_prep");
+  nrt_status st = sync_read_accum(c);
+  if (st) return st;
+  if (c->h_acc->invalid)
+    return fail(c, NRT_ERR_ARG, std::to_string(c->h_acc->invalid) +
+                                    " cells with n_H < 0, non-finite n_H or x outside [0,1]");
+  return NRT_OK;
+}
+
+}  // namespace
+
+namespace nrt {
+
+Layout plan_layout(const nrt_grid_desc& d, int64_t max_sources, int64_t capacity) {
+  Layout L;
+  std::memset(&L, 0, sizeof(L));
+  const int64_t cells = int64_t(d.n) * d.n * d.n;
+  L.cells = cells;
+  L.max_sources = max_sources;
+  L.capacity = capacity;
+  L.levels = d.l_max;
+  size_t off = 0;
+  L.n_H = off;
+  off = align256(off + size_t(cells) * 8);
+  L.x = off;
+  off = align256(off + size_t(cells) * 8);
+  L.a = off;
+  off = align256(off + size_t(cells) * (d.precision == NRT_MIXED ? 4 : 8));
+  L.srcpos = off;
+  off = align256(off + size_t(max_sources) * 24);
+  L.srcl0 = off;
+  off = align256(off + size_t(max_sources) * 8);
+  L.srcaux = off;
+  off = align256(off + size_t(max_sources) * 64);
+  L.queues = off;
+  const size_t per_level = align256(size_t(capacity) * 4) * 2 + align256(size_t(capacity) * 8) * 2;
+  off += per_level * size_t(L.levels);
+  L.accum = off;
+  off = align256(off + sizeof(Accum));
+  L.scratch = off;
+  // x_avg and x_new of the chemistry; also staging for injected rays and
+  // direction queries, hence a 4 MiB floor
+  off = align256(off + std::max<size_t>(size_t(cells) * 16, size_t(1) << 22));
+  L.total = off;
+  return L;
+}
+
+}  // namespace nrt
+
+extern "C" {
+
+const char* nrt_status_str(nrt_status s) {
+  switch (s) {
+    case NRT_OK: return "ok";
+    case NRT_ERR_ARG: return "invalid argument";
+    case NRT_ERR_STATE: return "invalid state";
+    case NRT_ERR_NOMEM: return "workspace too small";
+    case NRT_ERR_OVERFLOW: return "queue overflow";
+    case NRT_ERR_DEVICE: return "HIP error";
+    case NRT_ERR_INTERNAL: return "internal error";
+  }
+  return "unknown status";
+}
+
+const char* nrt_last_error(const nrt_ctx* c) {
+  return c ? c->err.c_str() : g_init_error.c_str();
+}
+
+nrt_status nrt_workspace_bytes(const nrt_grid_desc* desc, int64_t max_sources,
+                               int64_t ray_capacity, size_t* bytes) {
+  std::string why;
+  if (!check_desc(desc, why)) return fail(nullptr, NRT_ERR_ARG, why);
+  if (max_sources < 0 || max_sources > (int64_t(1) << 31))
+    return fail(nullptr, NRT_ERR_ARG, "max_sources out of range");
+  if (ray_capacity < 4096 || ray_capacity > (int64_t(1) << 32))
+    return fail(nullptr, NRT_ERR_ARG, "ray_capacity must be in [4096, 2^32]");
+  if (!bytes) return fail(nullptr, NRT_ERR_ARG, "bytes is NULL");
+  *bytes = nrt::plan_layout(*desc, max_sources, ray_capacity).total;
+  return NRT_OK;
+}
+
+nrt_status nrt_init_grid(nrt_ctx** out, const nrt_grid_desc* desc, const double* n_H,
+                         const double* x_ion, int64_t max_sources, int64_t ray_capacity,
+                         void* workspace, size_t ws_bytes, void* hip_stream) {
+  if (!out) return fail(nullptr, NRT_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  size_t need = 0;
+  nrt_status st = nrt_workspace_bytes(desc, max_sources, ray_capacity, &need);
+  if (st) return st;
+  if (!n_H || !x_ion || !workspace) return fail(nullptr, NRT_ERR_ARG, "NULL field or workspace");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256)
+    return fail(nullptr, NRT_ERR_ARG, "workspace must be 256-byte aligned");
+  if (ws_bytes < need)
+    return fail(nullptr, NRT_ERR_NOMEM,
+                "workspace has " + std::to_string(ws_bytes) + " bytes, needs " +
+                    std::to_string(need));
+  nrt_ctx* c = new (std::nothrow) nrt_ctx();
+  if (!c) return fail(nullptr, NRT_ERR_NOMEM, "host allocation failed");
+  c->desc = *desc;
+  c->lay = nrt::plan_layout(*desc, max_sources, ray_capacity);
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->ws = static_cast<char*>(workspace);
+  auto bail = [&](nrt_status s) {
+    g_init_error = c->err;
+    nrt_destroy(c);
+    return s;
+  };
+  hipError_t e = hipGetDevice(&c->device);
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, c->device);
+  if (e != hipSuccess) return bail(hip_fail(c, e, "device query"));
+  const Layout& L = c->lay;
+  c->n_H = reinterpret_cast<double*>(c->ws + L.n_H);
+  c->x = reinterpret_cast<double*>(c->ws + L.x);
+  c->a64 = desc->precision == NRT_MIXED ? nullptr : reinterpret_cast<double*>(c->ws + L.a);
+  c->a32 = desc->precision == NRT_MIXED ? reinterpret_cast<float*>(c->ws + L.a) : nullptr;
+  c->src_pos = reinterpret_cast<double*>(c->ws + L.srcpos);
+  c->src_l0 = reinterpret_cast<double*>(c->ws + L.srcl0);
+  char* q = c->ws + L.queues;
+  const size_t cap = size_t(L.capacity);
+  for (int l = 0; l <= nrt::kMaxLevel; ++l) c->queue[l] = RayQueue{nullptr, nullptr, nullptr, nullptr};
+  for (int l = 1; l <= L.levels; ++l) {
+    RayQueue& r = c->queue[l];
+    r.src = reinterpret_cast<uint32_t*>(q);
+    q += align256(cap * 4);
+    r.pix = reinterpret_cast<uint32_t*>(q);
+    q += align256(cap * 4);
+    r.s = reinterpret_cast<double*>(q);
+    q += align256(cap * 8);
+    r.w = reinterpret_cast<double*>(q);
+    q += align256(cap * 8);
+  }
+  c->acc = reinterpret_cast<Accum*>(c->ws + L.accum);
+  c->scratch = c->ws + L.scratch;
+  c->scratch_bytes = L.total - L.scratch;
+  c->sources_dirty = true;
+  level_constants(c);
+  e = hipHostMalloc(reinterpret_cast<void**>(&c->h_acc), sizeof(Accum), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    c->h_acc = nullptr;
+    return bail(hip_fail(c, e, "hipHostMalloc"));
+  }
+  const size_t fb = size_t(L.cells) * sizeof(double);
+  e = hipMemcpyAsync(c->n_H, n_H, fb, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->x, x_ion, fb, hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return bail(hip_fail(c, e, "field copy"));
+  st = prep_absorber(c, c->x);
+  if (st) return bail(st);
+  *out = c;
+  return NRT_OK;
+}
+
+nrt_status nrt_set_ionization(nrt_ctx* c, const double* x_ion) {
+  if (!c) return fail(nullptr, NRT_ERR_ARG, "ctx is NULL");
+  if (!x_ion) return fail(c, NRT_ERR_ARG, "x_ion is NULL");
+  double* xs = reinterpret_cast<double*>(c->scratch);
+  const size_t fb = size_t(c->lay.cells) * sizeof(double);
+  // validate on a scratch copy so that a rejected field leaves the context as it was
+  HIP_OR_FAIL(c, hipMemcpyAsync(xs, x_ion, fb, hipMemcpyDeviceToDevice, c->stream));
+  nrt_status st = prep_absorber(c, xs);
+  if (st) {
+    prep_absorber(c, c->x);
+    return st;
+  }
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->x, xs, fb, hipMemcpyDeviceToDevice, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return NRT_OK;
+}
+
+nrt_status nrt_get_ionization(nrt_ctx* c, double* x_out) {
+  if (!c) return fail(nullptr, NRT_ERR_ARG, "ctx is NULL");
+  if (!x_out) return fail(c, NRT_ERR_ARG, "x_out is NULL");
+  HIP_OR_FAIL(c, hipMemcpyAsync(x_out, c->x, size_t(c->lay.cells) * sizeof(double),
+                                hipMemcpyDeviceToDevice, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return NRT_OK;
+}
+
+nrt_status nrt_add_sources(nrt_ctx* c, int64_t m, const double* pos, const double* ndot) {
+  if (!c) return fail(nullptr, NRT_ERR_ARG, "ctx is NULL");
+  if (m < 0 || (m > 0 && (!pos || !ndot))) return fail(c, NRT_ERR_ARG, "bad source arrays");
+  const double n = double(c->desc.n);
+  for (int64_t k = 0; k < m; ++k) {
+    for (int a = 0; a < 3; ++a) {
+      const double p = pos[3 * k + a];
+      if (!(p >= 0.0 && p < n))
+        return fail(c, NRT_ERR_ARG, "source " + std::to_string(k) + " outside [0, n)");
+    }
+    if (!(ndot[k] >= 0.0) || !std::isfinite(ndot[k]))
+      return fail(c, NRT_ERR_ARG, "source " + std::to_string(k) + " has a bad rate");
+  }
+  if (int64_t(c->h_ndot.size()) + m > c->lay.max_sources)
+    return fail(c, NRT_ERR_OVERFLOW, "source table full");
+  c->h_pos.insert(c->h_pos.end(), pos, pos + 3 * m);
+  c->h_ndot.insert(c->h_ndot.end(), ndot, ndot + m);
+  c->h_radius.insert(c->h_radius.end(), size_t(m), 0.0);
+  c->sources_dirty = true;
+  return NRT_OK;
+}
+
+nrt_status nrt_clear_sources(nrt_ctx* c) {
+  if (!c) return fail(nullptr, NRT_ERR_ARG, "ctx is NULL");
+  c->h_pos.clear();
+  c->h_ndot.clear();
+  c->h_radius.clear();
+  c->sources_dirty = true;
+  return NRT_OK;
+}
+
+nrt_status nrt_source_count(const nrt_ctx* c, int64_t* m) {
+  if (!c || !m) return fail(const_cast<nrt_ctx*>(c), NRT_ERR_ARG, "NULL argument");
+  *m = int64_t(c->h_ndot.size());
+  return NRT_OK;
+}
+
+nrt_status nrt_get_sources(nrt_ctx* c, double* pos, double* ndot, double* radius) {
+  if (!c) return fail(nullptr, NRT_ERR_ARG, "ctx is NULL");
+  if (pos) std::copy(c->h_pos.begin(), c->h_pos.end(), pos);
+  if (ndot) std::copy(c->h_ndot.begin(), c->h_ndot.end(), ndot);
+  if (radius) std::copy(c->h_radius.begin(), c->h_radius.end(), radius);
+  return NRT_OK;
+}
+
+nrt_status nrt_trace_step(nrt_ctx* c, double* gamma_out, nrt_budget* budget) {
+  if (!c) return fail(nullptr, NRT_ERR_ARG, "ctx is NULL");
+  if (!gamma_out || !budget) return fail(c, NRT_ERR_ARG, "NULL gamma_out or budget");
+  return trace_pass(c, gamma_out, budget);
+}
+
+nrt_status nrt_trace_rays_debug(nrt_ctx* c, int64_t k, const double* origin, const double* dir,
+                                const int32_t* level, const double* L, double* gamma_out,
+                                nrt_budget* budget) {
+  if (!c) return fail(nullptr, NRT_ERR_ARG, "ctx is NULL");
+  if (c->desc.n_min_ray != 0.0) return fail(c, NRT_ERR_STATE, "injected rays need n_min_ray = 0");
+  if (k < 0 || (k > 0 && (!origin || !dir || !level || !L)) || !gamma_out || !budget)
+    return fail(c, NRT_ERR_ARG, "bad injected-ray arguments");
+  const size_t need = size_t(k) * 64;
+  if (need > c->scratch_bytes) return fail(c, NRT_ERR_NOMEM, "too many injected rays");
+  for (int64_t r = 0; r < k; ++r) {
+    for (int a = 0; a < 3; ++a)
+      if (!(origin[3 * r + a] >= 0.0 && origin[3 * r + a] < double(c->desc.n)))
+        return fail(c, NRT_ERR_ARG, "injected ray origin outside the box");
+    if (level[r] < 0 || level[r] > NRT_MAX_LEVEL || !(L[r] >= 0.0) || !std::isfinite(L[r]))
+      return fail(c, NRT_ERR_ARG, "bad injected ray level or rate");
+    // a direction must be a finite unit vector, or the march would not end
+    const double d0 = dir[3 * r], d1 = dir[3 * r + 1], d2 = dir[3 * r + 2];
+    const double nn = d0 * d0 + d1 * d1 + d2 * d2;
+    if (!std::isfinite(d0) || !std::isfinite(d1) || !std::isfinite(d2) || !(std::fabs(nn - 1.0) <= 1e-9))
+      return fail(c, NRT_ERR_ARG, "injected ray direction is not a unit vector");
+  }
+  double* d_org = reinterpret_cast<double*>(c->scratch);
+  double* d_dir = d_org + 3 * k;
+  double* d_L = d_dir + 3 * k;
+  int32_t* d_lev = reinterpret_cast<int32_t*>(d_L + k);
+  HIP_OR_FAIL(c, hipMemcpyAsync(d_org, origin, k * 24, hipMemcpyHostToDevice, c->stream));
+  HIP_OR_FAIL(c, hipMemcpyAsync(d_dir, dir, k * 24, hipMemcpyHostToDevice, c->stream));
+  HIP_OR_FAIL(c, hipMemcpyAsync(d_L, L, k * 8, hipMemcpyHostToDevice, c->stream));
+  HIP_OR_FAIL(c, hipMemcpyAsync(d_lev, level, k * 4, hipMemcpyHostToDevice, c->stream));
+  nrt_budget b;
+  std::memset(&b, 0, sizeof(b));
+  for (int64_t r = 0; r < k; ++r) {
+    b.emitted += L[r];
+    b.rays_per_level[level[r]] += 1;
+  }
+  b.rays = uint64_t(k);
+  HIP_OR_FAIL(c, nrt::launch_zero(gamma_out, c->lay.cells, c->cu_count, c->stream));
+  HIP_OR_FAIL(c, nrt::launch_zero_accum(c->acc, c->stream));
+  c->launches = 0;
+  if (k > 0) {
+    MarchArgs a = base_args(c, gamma_out);
+    a.level = -1;
+    a.begin = 0;
+    a.end = k;
+    a.inj_origin = d_org;
+    a.inj_dir = d_dir;
+    a.inj_L = d_L;
+    a.inj_level = d_lev;
+    a.out_cap = 0;
+    nrt_status st = launch_timed(c, a, k);
+    if (st) return st;
+  }
+  nrt_status st = sync_read_accum(c);
+  if (st) return st;
+  st = finish_timing(c);
+  if (st) return st;
+  b.absorbed = c->h_acc->absorbed;
+  b.escaped = c->h_acc->escaped;
+  b.truncated = c->h_acc->truncated;
+  b.segments = c->h_acc->segments;
+  *budget = b;
+  return NRT_OK;
+}
+
+nrt_status nrt_healpix_dirs(nrt_ctx* c, int32_t level, int64_t first, int64_t count,
+                            double* out) {
+  if (!c) return fail(nullptr, NRT_ERR_ARG, "ctx is NULL");
+  const int64_t npix = 12 * (int64_t(1) << (2 * std::max(0, level)));
+  if (level < 0 || level > NRT_MAX_LEVEL || first < 0 || count < 0 || first + count > npix ||
+      (count > 0 && !out))
+    return fail(c, NRT_ERR_ARG, "bad HEALPix range");
+  if (size_t(count) * 24 > c->scratch_bytes) return fail(c, NRT_ERR_NOMEM, "range too large");
+  if (count == 0) return NRT_OK;
+  double* d = reinterpret_cast<double*>(c->scratch);
+  HIP_OR_FAIL(c, nrt::launch_healpix(level, first, count, d, c->stream));
+  HIP_OR_FAIL(c, hipMemcpyAsync(out, d, size_t(count) * 24, hipMemcpyDeviceToHost, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return NRT_OK;
+}
+
+nrt_status nrt_rt_step(nrt_ctx* c, double dt_s, double alpha, double tol, int32_t max_iter,
+                       double* gamma_out, nrt_budget* budget, int32_t* iters) {
+  if (!c) return fail(nullptr, NRT_ERR_ARG, "ctx is NULL");
+  if (!(dt_s > 0.0) || !(alpha >= 0.0) || !(tol >= 0.0) || max_iter < 1 || !gamma_out ||
+      !budget)
+    return fail(c, NRT_ERR_ARG, "bad rt_step arguments");
+  double* x_avg = reinterpret_cast<double*>(c->scratch);
+  double* x_new = x_avg + c->lay.cells;
+  HIP_OR_FAIL(c, nrt::launch_copy(c, c->x, x_avg));
+  int32_t it = 1;
+  nrt_status st = NRT_OK;
+  for (;; ++it) {
+    st = prep_absorber(c, x_avg);
+    if (st) break;
+    st = trace_pass(c, gamma_out, budget);
+    if (st) break;
+    HIP_OR_FAIL(c, hipMemsetAsync(&c->acc->chem_delta_bits, 0, sizeof(unsigned long long),
+                                  c->stream));
+    HIP_OR_FAIL(c, nrt::launch_chem(c, gamma_out, dt_s, alpha, x_avg, x_new));
+    st = sync_read_accum(c);
+    if (st) break;
+    double delta;
+    std::memcpy(&delta, &c->h_acc->chem_delta_bits, sizeof(delta));
+    if (delta < tol || it >= max_iter) break;
+  }
+  if (st) {
+    prep_absorber(c, c->x);
+    return st;
+  }
+  HIP_OR_FAIL(c, nrt::launch_copy(c, x_new, c->x));
+  st = prep_absorber(c, c->x);
+  if (st) return st;
+  if (iters) *iters = it;
+  return NRT_OK;
+}
+
+nrt_status nrt_merge_sources(nrt_ctx* c, const nrt_merge_params* mp, int64_t* m_after) {
+  (void)mp;
+  (void)m_after;
+  return fail(c, NRT_ERR_STATE, "source merging is not available yet");
+}
+
+nrt_status nrt_last_kernel_time(const nrt_ctx* c, double* march_ms, int32_t* launches) {
+  if (!c) return fail(nullptr, NRT_ERR_ARG, "ctx is NULL");
+  if (march_ms) *march_ms = c->launches ? c->march_ms / c->launches : 0.0;
+  if (launches) *launches = c->launches;
+  return NRT_OK;
+}
+
+nrt_status nrt_destroy(nrt_ctx* c) {
+  if (!c) return NRT_OK;
+  (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  if (c->h_acc) (void)hipHostFree(c->h_acc);
+  delete c;
+  return NRT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Device-side HEALPix nested pixel centres (Gorski et al. 2005), the
+// pixelisation along which the paper's rays split (Sec. "Adaptive ray
+// tracing", Fig. raysplit).
+//
+// pix = face * Ns^2 + ipf with the in-face coordinates interleaved in ipf
+// (ix on even bits, iy on odd bits); ring jr = (face/4 + 2) Ns - ix - iy - 1;
+// cap rings have 1 - |z| = nr^2 / (3 Ns^2), belt rings z = (4Ns - 2jr)/(3Ns);
+// phi = (pi/4) (jpll nr + ix - iy) / nr.  The azimuth is evaluated in
+// [0, pi/4] and unfolded with exact swaps and sign changes, so mirror-image
+// pixels have exactly mirrored vectors; every step uses correctly rounded
+// FP64 operations except cos/sin.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace nrt {
+
+__device__ __forceinline__ uint32_t hp_compact(uint32_t v) {
+  v &= 0x55555555u;
+  v = (v | (v >> 1)) & 0x33333333u;
+  v = (v | (v >> 2)) & 0x0F0F0F0Fu;
+  v = (v | (v >> 4)) & 0x00FF00FFu;
+  v = (v | (v >> 8)) & 0x0000FFFFu;
+  return v;
+}
+
+__device__ inline void healpix_dir(int level, uint32_t pix, double& dx, double& dy, double& dz) {
+  const int64_t ns = int64_t(1) << level;
+  const uint32_t face = pix >> (2 * level);
+  const uint32_t ipf = pix - (face << (2 * level));
+  const int64_t ix = hp_compact(ipf);
+  const int64_t iy = hp_compact(ipf >> 1);
+  const int64_t row = face >> 2;  // 0 north, 1 equatorial, 2 south
+  const int64_t jr = (row + 2) * ns - ix - iy - 1;
+
+  int64_t nr;
+  double z, st;
+  if (jr < ns) {
+    nr = jr;
+    const double t = double(nr * nr) / double(3 * ns * ns);
+    z = 1.0 - t;
+    st = sqrt(t * (2.0 - t));
+  } else if (jr > 3 * ns) {
+    nr = 4 * ns - jr;
+    const double t = double(nr * nr) / double(3 * ns * ns);
+    z = t - 1.0;
+    st = sqrt(t * (2.0 - t));
+  } else {
+    nr = ns;
+    z = double(4 * ns - 2 * jr) / double(3 * ns);
+    st = sqrt((1.0 - z) * (1.0 + z));
+  }
+
+  const int64_t jpll = 2 * int64_t(face & 3u) + (row == 1 ? 0 : 1);
+  int64_t num = jpll * nr + ix - iy;  // phi = (pi/2) num / (2 nr)
+  if (num < 0) num += 8 * nr;
+  if (num >= 8 * nr) num -= 8 * nr;
+  const int64_t quad = num / (2 * nr);
+  const int64_t rem = num - quad * 2 * nr;
+
+  double c, s;
+  if (rem == 0) {
+    c = 1.0;
+    s = 0.0;
+  } else if (rem == nr) {
+    c = 0.70710678118654752440;  // sqrt(1/2), correctly rounded
+    s = c;
+  } else if (rem < nr) {
+    const double ang = (3.14159265358979323846 * double(rem)) / double(4 * nr);
+    c = cos(ang);
+    s = sin(ang);
+  } else {
+    const double ang = (3.14159265358979323846 * double(2 * nr - rem)) / double(4 * nr);
+    c = sin(ang);
+    s = cos(ang);
+  }
+  double cx, sy;
+  if (quad == 0) {
+    cx = c;
+    sy = s;
+  } else if (quad == 1) {
+    cx = -s;
+    sy = c;
+  } else if (quad == 2) {
+    cx = -c;
+    sy = -s;
+  } else {
+    cx = s;
+    sy = -c;
+  }
+  dx = st * cx;
+  dy = st * sy;
+  dz = z;
+}
+
+}  // namespace nrt

@@ -1,0 +1,131 @@
+// Internal declarations of the nyxrt library: context, workspace layout,
+// kernel argument blocks and kernel launchers.  Host code only sees the
+// launchers; every kernel lives in the .hip file that launches it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/nyxrt.h"
+
+namespace nrt {
+
+constexpr int kMaxLevel = NRT_MAX_LEVEL;
+constexpr int kBlock = 256;  // threads per block of the march kernels (4 waves)
+
+// One ray in a level queue (structure of arrays, 24 bytes per ray).  The
+// HEALPix level is the queue's, the rate follows from the source and level,
+// and the direction from (level, pix).  w is the optical depth tau (FP64
+// path) or the transmitted fraction exp(-tau) (mixed path).
+struct RayQueue {
+  uint32_t* src;
+  uint32_t* pix;
+  double* s;
+  double* w;
+};
+
+// Device accumulators of one pass.
+struct Accum {
+  double absorbed, escaped, truncated, pad;
+  unsigned long long segments;
+  unsigned long long overflow;
+  unsigned long long invalid;  // input cells failing validation
+  unsigned long long pad2;
+  unsigned long long out_count[kMaxLevel + 2];  // rays pushed into each level queue
+  unsigned long long chem_delta_bits;  // max |dx_avg| as the bits of a non-negative double
+};
+
+struct MarchArgs {
+  // grid
+  int32_t n, periodic, corr, l_max;
+  int32_t level;     // HEALPix level of every input ray (-1: injected rays)
+  int32_t spawn;     // 1: input ray r is (src_begin + r/12, pix r%12, s 0, w 0/1)
+  double h_cm, sigma0, tau_max, s_max, h3;
+  double r2split;    // split iff s*s > r2split (this level)
+  double sqrt_omega; // sqrt of the pixel solid angle (this level)
+  double t_min;      // exp(-tau_max): mixed-path termination threshold
+  float kf;          // (float)(sigma0 * h_cm)
+  const double* a64; // absorber, sign bit set = not a usable neighbour
+  const float* a32;
+  double* gamma;
+  // sources
+  const double* src_pos;  // 3 per source
+  const double* src_l0;   // rate per level-0 ray (ndot / 12)
+  int64_t src_begin;
+  // input rays [begin, end)
+  int64_t begin, end;
+  RayQueue in;
+  // injected rays (level == -1)
+  const double* inj_origin;
+  const double* inj_dir;
+  const int32_t* inj_level;
+  const double* inj_L;
+  double sqrt_omega_tab[kMaxLevel + 1];  // per level, for injected rays
+  // output rays (next level)
+  RayQueue out;
+  int64_t out_cap;
+  Accum* acc;
+};
+
+// Workspace carve-out (byte offsets into the caller's buffer).
+struct Layout {
+  size_t n_H, x, a, srcpos, srcl0, srcaux, queues, accum, scratch, total;
+  int64_t cells, max_sources, capacity;
+  int levels;  // number of level queues (levels 1..l_max)
+};
+
+Layout plan_layout(const nrt_grid_desc& d, int64_t max_sources, int64_t capacity);
+
+}  // namespace nrt
+
+struct nrt_ctx {
+  nrt_grid_desc desc;
+  nrt::Layout lay;
+  int device;
+  int cu_count;
+  hipStream_t stream;
+  char* ws;
+  // typed views into the workspace
+  double* n_H;
+  double* x;
+  double* a64;
+  float* a32;
+  double* src_pos;
+  double* src_l0;
+  nrt::RayQueue queue[nrt::kMaxLevel + 1];
+  nrt::Accum* acc;
+  char* scratch;
+  size_t scratch_bytes;
+  // host mirror of the source table
+  std::vector<double> h_pos, h_ndot, h_radius;
+  bool sources_dirty;
+  // pinned host staging for small readbacks
+  nrt::Accum* h_acc;
+  // per-level constants (host-computed, FP64)
+  double r2split[nrt::kMaxLevel + 1];
+  double sqrt_omega[nrt::kMaxLevel + 1];
+  // timing of the last pass
+  std::vector<hipEvent_t> ev;
+  int launches;
+  double march_ms;
+  std::string err;
+};
+
+namespace nrt {
+
+// trace.hip
+hipError_t launch_prep(nrt_ctx* c);
+hipError_t launch_zero(double* p, int64_t count, int cus, hipStream_t s);
+hipError_t launch_zero_accum(Accum* acc, hipStream_t s);
+hipError_t launch_march(const nrt_ctx* c, const MarchArgs& a, int64_t rays);
+hipError_t launch_healpix(int level, int64_t first, int64_t count, double* out, hipStream_t s);
+
+// chem.hip
+hipError_t launch_chem(const nrt_ctx* c, const double* gamma, double dt, double alpha,
+                       double* x_avg, double* x_new);
+hipError_t launch_copy(const nrt_ctx* c, const double* src, double* dst);
+
+}  // namespace nrt

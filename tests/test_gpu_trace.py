@@ -1,0 +1,251 @@
+"""GPU parity of the ray-tracing sweep against the oracle, through the C ABI.
+
+Bars (stated in the build's target): on cells with Gamma > 1e-6 max Gamma,
+the FP64 path matches the oracle to relative error 1e-10 and the mixed path
+to 1e-4; photon-budget terms match to 1e-6 of the emitted rate (FP64: 1e-10).
+Segment, ray and split counts are integers decided in FP64 on both sides and
+must be equal (the mixed path may differ only by rays whose tau_max
+termination flips, which the test bounds).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_err(got, ref, floor=1e-6):
+    got, ref = np.asarray(got), np.asarray(ref)
+    mask = ref > floor * ref.max()
+    e_in = np.abs(got[mask] / ref[mask] - 1).max() if mask.any() else 0.0
+    e_out = np.abs(got[~mask] - ref[~mask]).max() / ref.max() if (~mask).any() else 0.0
+    return e_in, e_out
+
+
+def budget_err(b, rb):
+    E = rb["emitted"]
+    return max(abs(b[k] - rb[k]) for k in ("absorbed", "escaped", "truncated")) / E
+
+
+def field_case(n, seed, ionized=0.3, m=5, mean=1e-3, tau_cell=0.5):
+    g = np.random.default_rng(seed)
+    nH = W.lognormal_density(n, mean, 1.0, g)
+    x = np.where(g.random((n, n, n)) < ionized, 1.0 - 1e-4, 0.0)
+    x[g.random((n, n, n)) < 0.03] = 1.0
+    pos = W.uniform_positions(m, n, g)
+    ndot = W.lognormal_values(m, 1e50, 1.0, g)
+    h = tau_cell / (W.SIGMA0 * mean)
+    return nH, x, pos, ndot, h
+
+
+def run_gpu(gpu, n, h, nH, x, pos, ndot, prec, cap=1 << 18, **kw):
+    ctx = gpu.init_grid(gpu.make_desc(n, h, precision=prec, **kw), nH, x, device="cuda:0",
+                        max_sources=max(len(ndot), 1), ray_capacity=cap)
+    ctx.add_sources(pos, ndot)
+    gamma, b = ctx.trace_step()
+    out = gamma.cpu().numpy()
+    ctx.destroy()
+    return out, b
+
+
+def test_device_healpix_matches_oracle(gpu, orc):
+    import workloads  # noqa: F401
+    n = 4
+    ctx = gpu.init_grid(gpu.make_desc(n, 1e20), np.ones((n, n, n)), np.zeros((n, n, n)),
+                        device="cuda:0", max_sources=1, ray_capacity=4096)
+    for level in range(0, 7):
+        dev = ctx.healpix_dirs(level)
+        ref = orc.healpix_dirs(level)
+        assert np.abs(dev - ref).max() <= 4.5e-16, level
+        # structured values are exact on both sides
+        np.testing.assert_array_equal(dev[ref == 0.0], 0.0)
+        np.testing.assert_array_equal(dev[:, 2], ref[:, 2])
+    last = 12 * 4 ** 14
+    dev = ctx.healpix_dirs(14, last - 64, 64)
+    np.testing.assert_allclose(np.linalg.norm(dev, axis=1), 1.0, atol=1e-15)
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_injected_rays(gpu, orc, periodic, prec):
+    n, h = 12, 3.0e19
+    g = np.random.default_rng(40 + periodic)
+    nH = W.lognormal_density(n, 1e-3, 1.0, g)
+    x = np.where(g.random((n, n, n)) < 0.3, 1.0, 0.0)
+    k = 300
+    o = g.random((k, 3)) * n
+    d = g.standard_normal((k, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    lev = g.integers(0, 6, k).astype(np.int32)
+    L = 10 ** g.uniform(40, 45, k)
+    kw = dict(periodic=periodic, n_min_ray=0.0, l_max=7, tau_max=30.0, n_th=4e-4)
+    ref, rb, _ = orc.trace_rays(orc.make_params(n, h, **kw), nH, x, o, d, lev, L)
+    ctx = gpu.init_grid(gpu.make_desc(n, h, precision=prec, **kw), nH, x, device="cuda:0",
+                        max_sources=1, ray_capacity=4096)
+    gamma, b = ctx.trace_rays_debug(o, d, lev, L)
+    ctx.destroy()
+    e_in, e_out = rel_err(gamma.cpu().numpy(), ref)
+    tol = 1e-12 if prec == 0 else 1e-4
+    assert e_in <= tol and e_out <= tol
+    assert b["segments"] == rb["segments"]
+    assert budget_err(b, rb) <= (1e-13 if prec == 0 else 1e-6)
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+@pytest.mark.parametrize("corr", [0, 1, 2, 3, 4])
+def test_trace_fp64_matches_oracle(gpu, orc, periodic, corr):
+    n = 24
+    nH, x, pos, ndot, h = field_case(n, 100 + corr + 10 * periodic)
+    kw = dict(periodic=periodic, n_min_ray=4.0, l_max=6, tau_max=25.0, n_th=4e-4, corr=corr)
+    ref, rb = orc.trace(orc.make_params(n, h, **kw), nH, x, pos, ndot)
+    got, b = run_gpu(gpu, n, h, nH, x, pos, ndot, 0, **kw)
+    e_in, e_out = rel_err(got, ref)
+    assert e_in <= 1e-10 and e_out <= 1e-10, (e_in, e_out)
+    for k in ("segments", "rays", "splits"):
+        assert b[k] == rb[k], k
+    assert b["rays_per_level"] == rb["rays_per_level"][:15]
+    assert budget_err(b, rb) <= 1e-10
+    assert b["emitted"] == rb["emitted"]
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+@pytest.mark.parametrize("corr", [2, 4])
+def test_trace_mixed_matches_oracle(gpu, orc, periodic, corr):
+    n = 24
+    nH, x, pos, ndot, h = field_case(n, 200 + corr + 10 * periodic)
+    kw = dict(periodic=periodic, n_min_ray=4.0, l_max=6, tau_max=25.0, n_th=4e-4, corr=corr)
+    ref, rb = orc.trace(orc.make_params(n, h, **kw), nH, x, pos, ndot)
+    got, b = run_gpu(gpu, n, h, nH, x, pos, ndot, 1, **kw)
+    e_in, _ = rel_err(got, ref)
+    assert e_in <= 1e-4, e_in
+    E = b["emitted"]
+    assert abs(b["absorbed"] + b["escaped"] + b["truncated"] - E) <= 1e-12 * E
+    assert budget_err(b, rb) <= 1e-6
+    # crossings and split tests are FP64 decisions shared with the FP64 path;
+    # the tau_max stop uses the FP32-accumulated transmission and runs before
+    # the split test, so a ray within rounding of tau_max (carrying less than
+    # e^-25 of its photons) may march a few more cells or split once more
+    for k in ("segments", "rays", "splits"):
+        assert abs(b[k] - rb[k]) <= 1e-4 * rb[k], k
+
+
+def test_small_queues_chunk_and_recurse(gpu, orc):
+    """A 4096-slot queue forces every level to be processed in many chunks,
+    depth first; the result must not depend on the queue size."""
+    n = 32
+    nH, x, pos, ndot, h = field_case(n, 7, ionized=0.6, m=3, tau_cell=0.2)
+    kw = dict(periodic=True, n_min_ray=4.0, l_max=7, tau_max=30.0, n_th=4e-4)
+    ref, rb = orc.trace(orc.make_params(n, h, **kw), nH, x, pos, ndot)
+    small, bs = run_gpu(gpu, n, h, nH, x, pos, ndot, 0, cap=4096, **kw)
+    big, bb = run_gpu(gpu, n, h, nH, x, pos, ndot, 0, cap=1 << 20, **kw)
+    assert max(rb["rays_per_level"]) > 4 * 4096
+    for got, b in ((small, bs), (big, bb)):
+        assert rel_err(got, ref)[0] <= 1e-10
+        assert b["segments"] == rb["segments"] and b["rays"] == rb["rays"]
+    np.testing.assert_allclose(small, big, rtol=1e-12, atol=1e-14 * big.max())
+
+
+def test_edge_cases(gpu, orc):
+    # no sources: Gamma = 0, empty budget
+    n = 8
+    nH, x = np.full((n, n, n), 1e-3), np.zeros((n, n, n))
+    h = 1e20
+    got, b = run_gpu(gpu, n, h, nH, x, np.zeros((0, 3)), np.zeros(0), 0)
+    assert not got.any() and b["emitted"] == 0 and b["segments"] == 0
+    # a one-cell grid, periodic and open
+    for periodic in (True, False):
+        kw = dict(periodic=periodic, n_min_ray=4.0, l_max=5, tau_max=30.0)
+        one = (np.full((1, 1, 1), 1e-3), np.zeros((1, 1, 1)))
+        ref, rb = orc.trace(orc.make_params(1, h, **kw), *one, [[0.3, 0.6, 0.9]], [1e49])
+        got, b = run_gpu(gpu, 1, h, *one, [[0.3, 0.6, 0.9]], [1e49], 0, **kw)
+        assert rel_err(got, ref)[0] <= 1e-12 and b["segments"] == rb["segments"]
+    # structured ties: cell-centred and integer-coordinate sources, zero rate
+    n = 16
+    nH, x = np.full((n, n, n), 1e-3), np.zeros((n, n, n))
+    x[4:12, 4:12, 4:12] = 1.0 - 1e-4
+    pos = np.array([[8.5, 8.5, 8.5], [8.0, 8.0, 8.0], [0.0, 0.0, 0.0], [3.5, 12.0, 7.25]])
+    ndot = np.array([1e50, 3e49, 2e49, 0.0])
+    for periodic in (True, False):
+        kw = dict(periodic=periodic, n_min_ray=4.0, l_max=6, tau_max=30.0, n_th=1e-5)
+        ref, rb = orc.trace(orc.make_params(n, 2e20, **kw), nH, x, pos, ndot)
+        got, b = run_gpu(gpu, n, 2e20, nH, x, pos, ndot, 0, **kw)
+        assert rel_err(got, ref)[0] <= 1e-10
+        assert b["segments"] == rb["segments"] and b["splits"] == rb["splits"]
+
+
+def test_invalid_inputs_rejected(gpu):
+    n = 8
+    nH, x = np.full((n, n, n), 1e-3), np.zeros((n, n, n))
+    d = gpu.make_desc(n, 1e20)
+    bad = x.copy()
+    bad[1, 2, 3] = 1.5
+    with pytest.raises(gpu.NyxRTError) as e:
+        gpu.init_grid(d, nH, bad, device="cuda:0", max_sources=4, ray_capacity=4096)
+    assert e.value.status == 1
+    ctx = gpu.init_grid(d, nH, x, device="cuda:0", max_sources=2, ray_capacity=4096)
+    with pytest.raises(gpu.NyxRTError):
+        ctx.add_sources([[8.0, 1.0, 1.0]], [1.0])  # outside [0, n)
+    with pytest.raises(gpu.NyxRTError):
+        ctx.add_sources([[1.0, 1.0, 1.0]], [-1.0])
+    with pytest.raises(gpu.NyxRTError) as e:
+        ctx.add_sources(np.ones((3, 3)), np.ones(3))  # table holds 2
+    assert e.value.status == 4
+    assert ctx.source_count() == 0
+    with pytest.raises(gpu.NyxRTError):
+        ctx.set_ionization(bad)
+    # a rejected field leaves the context's field unchanged
+    np.testing.assert_array_equal(ctx.get_ionization().cpu().numpy(), x)
+    ctx.destroy()
+
+
+@pytest.mark.slow
+def test_full_lognormal_128_fp64_and_mixed(gpu, orc):
+    """The 128^3 lognormal workload with all 64 sources at full size, in the
+    launch configuration of the benchmark: FP64 against the oracle
+    everywhere, mixed against the oracle, and source superposition."""
+    w = W.config2()
+    kw = dict(periodic=w.periodic, n_min_ray=w.n_min_ray, l_max=w.l_max, tau_max=w.tau_max,
+              n_th=w.n_th)
+    ref, rb = orc.trace(orc.make_params(w.n, w.h_cm, **kw), w.n_H, w.x, w.pos, w.ndot)
+    got, b = run_gpu(gpu, w.n, w.h_cm, w.n_H, w.x, w.pos, w.ndot, 0, cap=1 << 22, **kw)
+    assert rel_err(got, ref)[0] <= 1e-10
+    assert b["segments"] == rb["segments"] and b["splits"] == rb["splits"]
+    assert budget_err(b, rb) <= 1e-10
+    gm, bm = run_gpu(gpu, w.n, w.h_cm, w.n_H, w.x, w.pos, w.ndot, 1, cap=1 << 22, **kw)
+    assert rel_err(gm, ref)[0] <= 1e-4
+    assert budget_err(bm, rb) <= 1e-6
+    half = len(w.ndot) // 2
+    g1, _ = run_gpu(gpu, w.n, w.h_cm, w.n_H, w.x, w.pos[:half], w.ndot[:half], 0, **kw)
+    g2, _ = run_gpu(gpu, w.n, w.h_cm, w.n_H, w.x, w.pos[half:], w.ndot[half:], 0, **kw)
+    np.testing.assert_allclose(g1 + g2, got, rtol=1e-12, atol=1e-13 * got.max())
+
+
+def test_rt_step_stromgren(gpu, orc):
+    """Config 1 (Stromgren Test A): three radiation steps on the GPU against
+    the oracle's, and the radius against the closed form."""
+    w = W.config1()
+    kw = dict(periodic=False, n_min_ray=w.n_min_ray, l_max=w.l_max, tau_max=w.tau_max,
+              n_th=w.n_th)
+    alpha = w.extra["alpha_B"] * w.extra["clumping"]
+    dt = w.extra["dt_s"]
+    p = orc.make_params(w.n, w.h_cm, **kw)
+    ctx = gpu.init_grid(gpu.make_desc(w.n, w.h_cm, **kw), w.n_H, w.x, device="cuda:0",
+                        max_sources=1, ray_capacity=1 << 18)
+    ctx.add_sources(w.pos, w.ndot)
+    x_ref = w.x.copy()
+    r_s = (3 * w.ndot[0] / (4 * math.pi * alpha * 1e-6)) ** (1 / 3) / w.h_cm
+    t_rec = 1 / (alpha * 1e-3)
+    for step in range(1, 4):
+        x_ref, g_ref, b_ref, it_ref = orc.rt_step(p, w.n_H, x_ref, w.pos, w.ndot, dt, alpha)
+        g, b, it = ctx.rt_step(dt, alpha)
+        x_gpu = ctx.get_ionization().cpu().numpy()
+        assert abs(it - it_ref) <= 1
+        assert np.abs(x_gpu - x_ref).max() <= 1e-6
+        r_n = (3 * x_gpu.sum() / (4 * math.pi)) ** (1 / 3)
+        r_a = r_s * (1 - math.exp(-step * dt / t_rec)) ** (1 / 3)
+        assert r_n / r_a == pytest.approx(1.0, abs=0.02)
+    ctx.destroy()
