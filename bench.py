@@ -108,6 +108,9 @@ def main():
     ap.add_argument("--paths", default="mixed,fp64")
     ap.add_argument("--cpu-sources", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device three times (a kernel of known "
+                         "traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path "
@@ -118,6 +121,14 @@ def main():
     import paper_2512_12466_amd as nrt
     nrt.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy << 17, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: 3 x {args.calibrate_copy} MiB")
+        del src, dst
     w = make_workload(args.workload)
     res = {}
     for path in args.paths.split(","):

@@ -88,7 +88,7 @@ typedef struct {
   double r_max;        /* radius cap [cells]                            */
   double f_ov;         /* overlap factor                                */
   double eps;          /* squared-distance tolerance [cells^2]          */
-  int32_t shell_level; /* HEALPix level of the shell directions, 0..6   */
+  int32_t shell_level; /* HEALPix level of the shell directions, 0..3   */
 } nrt_merge_params;
 
 /* Photon budget of one pass: emitted = absorbed + escaped + truncated. */

@@ -9,6 +9,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libnyxrt.so")
 SOURCES = ["capi.hip", "trace.hip", "chem.hip", "merge.hip"]
 ARCH = os.environ.get("NYXRT_OFFLOAD_ARCH", "gfx950")
@@ -27,7 +28,7 @@ def sources():
 
 
 def build(verbose: bool = False, extra=()) -> str:
-    cmd = [HIPCC] + FLAGS + list(extra) + sources() + ["-o", LIB + ".tmp"]
+    cmd = [HIPCC] + FLAGS + ["-I" + INCLUDE] + list(extra) + sources() + ["-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True, cwd=CSRC)

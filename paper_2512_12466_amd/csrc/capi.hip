@@ -115,6 +115,7 @@ MarchArgs base_args(const nrt_ctx* c, double* gamma) {
   a.src_l0 = c->src_l0;
   for (int l = 0; l <= nrt::kMaxLevel; ++l) a.sqrt_omega_tab[l] = c->sqrt_omega[l];
   a.acc = c->acc;
+  a.lds_keys_fit = (int64_t(d.n) * d.n * d.n < (int64_t(1) << 32) - 1) ? 1 : 0;
   return a;
 }
 
@@ -266,7 +267,8 @@ Layout plan_layout(const nrt_grid_desc& d, int64_t max_sources, int64_t capacity
   L.srcl0 = off;
   off = align256(off + size_t(max_sources) * 8);
   L.srcaux = off;
-  off = align256(off + size_t(max_sources) * 64);
+  // merge scratch: per-source arrays plus the alignment of its 15 sub-buffers
+  off = align256(off + size_t(max_sources) * nrt::merge_bytes_per_source() + 16 * 256);
   L.queues = off;
   const size_t per_level = align256(size_t(capacity) * 4) * 2 + align256(size_t(capacity) * 8) * 2;
   off += per_level * size_t(L.levels);
@@ -579,9 +581,38 @@ nrt_status nrt_rt_step(nrt_ctx* c, double dt_s, double alpha, double tol, int32_
 }
 
 nrt_status nrt_merge_sources(nrt_ctx* c, const nrt_merge_params* mp, int64_t* m_after) {
-  (void)mp;
-  (void)m_after;
-  return fail(c, NRT_ERR_STATE, "source merging is not available yet");
+  if (!c) return fail(nullptr, NRT_ERR_ARG, "ctx is NULL");
+  if (!mp || !m_after) return fail(c, NRT_ERR_ARG, "NULL merge parameters or m_after");
+  if (!(mp->dr > 0.0) || !std::isfinite(mp->dr) || std::isnan(mp->x_th) ||
+      !std::isfinite(mp->f_req) || mp->n_min < 0 || !(mp->r_max >= 0.0) ||
+      !std::isfinite(mp->r_max) || !(mp->f_ov >= 0.0) || !std::isfinite(mp->f_ov) ||
+      !(mp->eps >= 0.0) || !std::isfinite(mp->eps) || mp->shell_level < 0 ||
+      mp->shell_level > 3)
+    return fail(c, NRT_ERR_ARG, "bad merge parameters (shell_level must be 0..3)");
+  const int64_t m = int64_t(c->h_ndot.size());
+  if (m == 0) {
+    *m_after = 0;
+    return NRT_OK;
+  }
+  nrt_status st = upload_sources(c);
+  if (st) return st;
+  std::vector<double> out6;
+  std::string why;
+  hipError_t e = nrt::run_merge(c, *mp, c->h_ndot.data(), m, out6, why);
+  if (e != hipSuccess)
+    return why.empty() ? hip_fail(c, e, "source merge") : fail(c, NRT_ERR_NOMEM, why);
+  const size_t m2 = out6.size() / 6;
+  c->h_pos.resize(3 * m2);
+  c->h_ndot.resize(m2);
+  c->h_radius.resize(m2);
+  for (size_t k = 0; k < m2; ++k) {
+    for (int a = 0; a < 3; ++a) c->h_pos[3 * k + a] = out6[6 * k + a];
+    c->h_ndot[k] = out6[6 * k + 3];
+    c->h_radius[k] = out6[6 * k + 4];
+  }
+  c->sources_dirty = true;
+  *m_after = int64_t(m2);
+  return NRT_OK;
 }
 
 nrt_status nrt_last_kernel_time(const nrt_ctx* c, double* march_ms, int32_t* launches) {

@@ -9,7 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/nyxrt.h"
+#include "nyxrt.h"
 
 namespace nrt {
 
@@ -43,6 +43,7 @@ struct MarchArgs {
   int32_t n, periodic, corr, l_max;
   int32_t level;     // HEALPix level of every input ray (-1: injected rays)
   int32_t spawn;     // 1: input ray r is (src_begin + r/12, pix r%12, s 0, w 0/1)
+  int32_t lds_keys_fit;  // 1: flat cell indices fit 32 bits (Gamma staged in LDS)
   double h_cm, sigma0, tau_max, s_max, h3;
   double r2split;    // split iff s*s > r2split (this level)
   double sqrt_omega; // sqrt of the pixel solid angle (this level)
@@ -122,6 +123,11 @@ hipError_t launch_zero(double* p, int64_t count, int cus, hipStream_t s);
 hipError_t launch_zero_accum(Accum* acc, hipStream_t s);
 hipError_t launch_march(const nrt_ctx* c, const MarchArgs& a, int64_t rays);
 hipError_t launch_healpix(int level, int64_t first, int64_t count, double* out, hipStream_t s);
+
+// merge.hip
+size_t merge_bytes_per_source();
+hipError_t run_merge(nrt_ctx* c, const nrt_merge_params& mp, const double* h_ndot, int64_t m,
+                     std::vector<double>& out6, std::string& why);
 
 // chem.hip
 hipError_t launch_chem(const nrt_ctx* c, const double* gamma, double dt, double alpha,

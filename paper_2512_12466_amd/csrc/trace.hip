@@ -14,6 +14,7 @@
 // the optical depth, attenuation and deposits in FP32 from an FP32 absorber
 // and tracks the transmitted fraction in FP64.
 #include <cfloat>
+#include <type_traits>
 
 #include "healpix.h"
 #include "internal.h"
@@ -68,13 +69,64 @@ struct LaneAcc {
   unsigned long long segments = 0;
 };
 
+// Per-block Gamma accumulator in LDS.  The rays of one block are a bundle of
+// neighbouring HEALPix pixels of one source and level (nested pixel order is
+// a Z-order curve and children are queued next to each other), so they cross
+// the same cells several times; deposits are summed in an open-addressing
+// hash table keyed by the cell index and flushed to Gamma with one global
+// atomic per distinct cell.  A deposit that finds no slot within kProbe
+// probes goes straight to global memory.
+constexpr int kSlots = 4096;
+constexpr int kProbe = 16;
+constexpr uint32_t kEmpty = 0xffffffffu;
+
+template <typename V>
+struct DepositTable {
+  uint32_t* key;
+  V* val;
+  double* gamma;
+  bool on;  // false when cell indices do not fit 32 bits
+
+  __device__ __forceinline__ void add(int64_t c, V v) const {
+    if (on) {
+      const uint32_t k = uint32_t(c);
+      uint32_t h = (k * 2654435761u) >> (32 - 12);
+#pragma unroll 1
+      for (int probe = 0; probe < kProbe; ++probe) {
+        const uint32_t old = atomicCAS(&key[h], kEmpty, k);
+        if (old == kEmpty || old == k) {
+          atomicAdd(&val[h], v);
+          return;
+        }
+        h = (h + 1) & (kSlots - 1);
+      }
+    }
+    atomicAdd(gamma + c, double(v));
+  }
+
+  // all threads of the block: fold the table into Gamma and clear it
+  __device__ __forceinline__ void flush() const {
+    __syncthreads();
+    for (int q = threadIdx.x; q < kSlots; q += blockDim.x) {
+      const uint32_t k = key[q];
+      if (k != kEmpty) {
+        atomicAdd(gamma + k, double(val[q]));
+        key[q] = kEmpty;
+        val[q] = V(0);
+      }
+    }
+    __syncthreads();
+  }
+};
+
 // March one ray from distance s until it stops.  o: source position, d:
 // unit direction, L: photon rate of the ray, w: tau (FP64) or exp(-tau)
 // (MIXED).  On a split, `split` is set and s_out / w_out carry the state
 // the children start from.  Unwrapped cell coordinates (i) keep the plane
 // crossings exact across periodic wraps; wrapped ones (w) address memory.
 template <bool MIXED>
-__device__ void march_ray(const MarchArgs& A, double o0, double o1, double o2, double d0,
+__device__ void march_ray(const MarchArgs& A, const DepositTable<typename std::conditional<MIXED, float, double>::type>& tab,
+                          double o0, double o1, double o2, double d0,
                           double d1, double d2, double L, int level, double r2split,
                           double sqrt_omega, double s, double w, LaneAcc& acc, bool& split,
                           double& s_out, double& w_out) {
@@ -245,13 +297,13 @@ __device__ void march_ray(const MarchArgs& A, double o0, double o1, double o2, d
     }
 
     // ---- deposit ----
-    if (MIXED) {
+    if constexpr (MIXED) {
       const float fcf = float(fc);
-      atomicAdd(A.gamma + c, double(fcf * G32));
-      if (secondary) atomicAdd(A.gamma + c2, double(((1.0f - fcf) * (a32 / a2_32)) * G32));
+      tab.add(c, fcf * G32);
+      if (secondary) tab.add(c2, ((1.0f - fcf) * (a32 / a2_32)) * G32);
     } else {
-      atomicAdd(A.gamma + c, fc * G64);
-      if (secondary) atomicAdd(A.gamma + c2, ((1.0 - fc) * (a64 / a2_64)) * G64);
+      tab.add(c, fc * G64);
+      if (secondary) tab.add(c2, ((1.0 - fc) * (a64 / a2_64)) * G64);
     }
 
     // ---- advance one cell ----
@@ -280,6 +332,17 @@ __device__ void march_ray(const MarchArgs& A, double o0, double o1, double o2, d
 
 template <bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_march(MarchArgs A) {
+  using V = typename std::conditional<MIXED, float, double>::type;
+  // the deposit table, reused for the budget reduction at the end
+  __shared__ __align__(16) unsigned char lds[kSlots * (sizeof(uint32_t) + sizeof(V))];
+  uint32_t* lds_key = reinterpret_cast<uint32_t*>(lds);
+  V* lds_val = reinterpret_cast<V*>(lds + kSlots * sizeof(uint32_t));
+  const DepositTable<V> tab{lds_key, lds_val, A.gamma, A.lds_keys_fit != 0};
+  for (int q = threadIdx.x; q < kSlots; q += kBlock) {
+    lds_key[q] = kEmpty;
+    lds_val[q] = V(0);
+  }
+  __syncthreads();
   LaneAcc acc;
   const int lane = __lane_id();
   const int64_t stride = int64_t(gridDim.x) * kBlock;
@@ -325,9 +388,10 @@ __global__ __launch_bounds__(kBlock) void k_march(MarchArgs A) {
         r2s = A.r2split;
         sqo = A.sqrt_omega;
       }
-      march_ray<MIXED>(A, o0, o1, o2, d0, d1, d2, L, level, r2s, sqo, s, w, acc, split, s_out,
-                       w_out);
+      march_ray<MIXED>(A, tab, o0, o1, o2, d0, d1, d2, L, level, r2s, sqo, s, w, acc, split,
+                       s_out, w_out);
     }
+    tab.flush();
     // children of the rays that split: one allocation per wavefront
     const uint64_t mask = __ballot(split);
     if (mask) {
@@ -355,8 +419,10 @@ __global__ __launch_bounds__(kBlock) void k_march(MarchArgs A) {
   }
 
   // block reduction of the lane budgets, then one atomic per block and term
-  __shared__ double red_d[3][kBlock];
-  __shared__ unsigned long long red_u[kBlock];
+  // (the deposit table is empty after its last flush)
+  static_assert(kSlots * (sizeof(uint32_t) + sizeof(V)) >= kBlock * 32, "reduction space");
+  double(*red_d)[kBlock] = reinterpret_cast<double(*)[kBlock]>(lds);
+  unsigned long long* red_u = reinterpret_cast<unsigned long long*>(lds + 3 * kBlock * 8);
   red_d[0][threadIdx.x] = acc.absorbed;
   red_d[1][threadIdx.x] = acc.escaped;
   red_d[2][threadIdx.x] = acc.truncated;
