@@ -186,6 +186,24 @@ nrt_status nrt_trace_rays_debug(nrt_ctx* ctx, int64_t k, const double* origin, c
 nrt_status nrt_healpix_dirs(nrt_ctx* ctx, int32_t level, int64_t first, int64_t count,
                             double* out);
 
+/* Launch parameters of the march kernel.  0 selects the built-in default. */
+typedef struct {
+  int32_t refill_min;    /* idle lanes that make a wavefront fetch new rays (1..64) */
+  int32_t claim;         /* rays a wavefront claims at a time (64..65536, multiple of 64) */
+  int32_t blocks_per_cu; /* resident 256-thread blocks per compute unit               */
+} nrt_tuning;
+
+/* Set (or read back) the march launch parameters of a context.  Results
+   do not depend on them; only the speed does.  NRT_ERR_ARG when out of range. */
+nrt_status nrt_set_tuning(nrt_ctx* ctx, const nrt_tuning* t);
+nrt_status nrt_get_tuning(const nrt_ctx* ctx, nrt_tuning* t);
+
+/* Autotuner: run one trace pass (into gamma_scratch, device n^3 FP64) per
+   candidate parameter set, time the march kernels with HIP events, keep the
+   fastest in the context and return it in *best (host).  `passes` repeats
+   each candidate (>= 1).  Uses the context's current grid and sources. */
+nrt_status nrt_autotune(nrt_ctx* ctx, double* gamma_scratch, int32_t passes, nrt_tuning* best);
+
 /* Average duration [ms] of the march kernel launches of the last
    nrt_trace_step, timed with HIP events on the context's stream, and the
    number of those launches. */

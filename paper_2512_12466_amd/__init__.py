@@ -40,6 +40,13 @@ class MergeParams(C.Structure):
                 ("eps", C.c_double), ("shell_level", C.c_int32)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("refill_min", C.c_int32), ("claim", C.c_int32), ("blocks_per_cu", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Budget(C.Structure):
     _fields_ = [("emitted", C.c_double), ("absorbed", C.c_double),
                 ("escaped", C.c_double), ("truncated", C.c_double),
@@ -86,6 +93,9 @@ def load():
                                       C.POINTER(Budget)]),
         "nrt_healpix_dirs": (st, [_P, C.c_int32, C.c_int64, C.c_int64, _D]),
         "nrt_last_kernel_time": (st, [_P, _D, C.POINTER(C.c_int32)]),
+        "nrt_set_tuning": (st, [_P, C.POINTER(Tuning)]),
+        "nrt_get_tuning": (st, [_P, C.POINTER(Tuning)]),
+        "nrt_autotune": (st, [_P, _P, C.c_int32, C.POINTER(Tuning)]),
         "nrt_destroy": (st, [_P]),
         "nrt_status_str": (C.c_char_p, [C.c_int]),
         "nrt_last_error": (C.c_char_p, [_P]),
@@ -250,6 +260,24 @@ class Context:
         n = C.c_int32(0)
         _check(load().nrt_last_kernel_time(self._ctx, C.byref(ms), C.byref(n)), self._ctx)
         return ms.value, n.value
+
+    def set_tuning(self, refill_min=0, claim=0, blocks_per_cu=0):
+        _check(load().nrt_set_tuning(self._ctx, C.byref(Tuning(refill_min, claim,
+                                                                blocks_per_cu))), self._ctx)
+
+    def get_tuning(self):
+        t = Tuning()
+        _check(load().nrt_get_tuning(self._ctx, C.byref(t)), self._ctx)
+        return t.as_dict()
+
+    def autotune(self, passes=1, gamma=None):
+        """nrt_autotune: time candidate launch parameters on this context's
+        workload, keep and return the fastest."""
+        gamma = self._gamma(gamma)
+        t = Tuning()
+        _check(load().nrt_autotune(self._ctx, gamma.data_ptr(), int(passes), C.byref(t)),
+               self._ctx)
+        return t.as_dict()
 
     def destroy(self):
         if getattr(self, "_ctx", None):

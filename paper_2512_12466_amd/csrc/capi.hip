@@ -166,6 +166,7 @@ nrt_status process_level(nrt_ctx* c, PassState& ps, int level, bool spawn, int64
       a.out = c->queue[level];
       a.out_cap = 0;
     }
+    HIP_OR_FAIL(c, hipMemsetAsync(&c->acc->claim, 0, sizeof(unsigned long long), c->stream));
     nrt_status st = launch_timed(c, a, e - b);
     if (st) return st;
     ps.b->rays_per_level[level] += uint64_t(e - b);
@@ -345,6 +346,8 @@ nrt_status nrt_init_grid(nrt_ctx** out, const nrt_grid_desc* desc, const double*
   hipError_t e = hipGetDevice(&c->device);
   if (e == hipSuccess)
     e = hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, c->device);
+  if (e == hipSuccess)
+    e = nrt::march_blocks_per_cu(desc->precision == NRT_MIXED, &c->march_blocks_per_cu);
   if (e != hipSuccess) return bail(hip_fail(c, e, "device query"));
   const Layout& L = c->lay;
   c->n_H = reinterpret_cast<double*>(c->ws + L.n_H);
@@ -513,6 +516,7 @@ nrt_status nrt_trace_rays_debug(nrt_ctx* c, int64_t k, const double* origin, con
     a.inj_L = d_L;
     a.inj_level = d_lev;
     a.out_cap = 0;
+    HIP_OR_FAIL(c, hipMemsetAsync(&c->acc->claim, 0, sizeof(unsigned long long), c->stream));
     nrt_status st = launch_timed(c, a, k);
     if (st) return st;
   }
@@ -612,6 +616,58 @@ nrt_status nrt_merge_sources(nrt_ctx* c, const nrt_merge_params* mp, int64_t* m_
   }
   c->sources_dirty = true;
   *m_after = int64_t(m2);
+  return NRT_OK;
+}
+
+nrt_status nrt_set_tuning(nrt_ctx* c, const nrt_tuning* t) {
+  if (!c) return fail(nullptr, NRT_ERR_ARG, "ctx is NULL");
+  if (!t) return fail(c, NRT_ERR_ARG, "tuning is NULL");
+  if (t->refill_min < 0 || t->refill_min > 64 || t->claim < 0 || t->claim > 65536 ||
+      t->claim % 64 != 0 || t->blocks_per_cu < 0 || t->blocks_per_cu > 64)
+    return fail(c, NRT_ERR_ARG, "tuning out of range");
+  c->tuning = *t;
+  return NRT_OK;
+}
+
+nrt_status nrt_get_tuning(const nrt_ctx* c, nrt_tuning* t) {
+  if (!c || !t) return fail(const_cast<nrt_ctx*>(c), NRT_ERR_ARG, "NULL argument");
+  *t = c->tuning;
+  return NRT_OK;
+}
+
+nrt_status nrt_autotune(nrt_ctx* c, double* gamma_scratch, int32_t passes, nrt_tuning* best) {
+  if (!c) return fail(nullptr, NRT_ERR_ARG, "ctx is NULL");
+  if (!gamma_scratch || !best || passes < 1) return fail(c, NRT_ERR_ARG, "bad autotune arguments");
+  const nrt_tuning keep = c->tuning;
+  std::vector<nrt_tuning> cand;
+  const int max_bpc = std::max(1, c->march_blocks_per_cu);
+  for (int refill : {1, 4, 8, 16, 32})
+    for (int claim : {0, 256, 1024})
+      for (int bpc : {0, std::max(1, max_bpc - 1)}) {
+        if (bpc != 0 && bpc == max_bpc) continue;
+        cand.push_back(nrt_tuning{refill, claim, bpc});
+      }
+  double best_ms = INFINITY;
+  nrt_tuning win = keep;
+  for (const nrt_tuning& t : cand) {
+    c->tuning = t;
+    double ms = 0.0;
+    for (int p = 0; p < passes; ++p) {
+      nrt_budget b;
+      nrt_status st = trace_pass(c, gamma_scratch, &b);
+      if (st) {
+        c->tuning = keep;
+        return st;
+      }
+      ms += c->march_ms;
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      win = t;
+    }
+  }
+  c->tuning = win;
+  *best = win;
   return NRT_OK;
 }
 

@@ -33,7 +33,7 @@ struct Accum {
   unsigned long long segments;
   unsigned long long overflow;
   unsigned long long invalid;  // input cells failing validation
-  unsigned long long pad2;
+  unsigned long long claim;  // rays claimed so far in the current march launch
   unsigned long long out_count[kMaxLevel + 2];  // rays pushed into each level queue
   unsigned long long chem_delta_bits;  // max |dx_avg| as the bits of a non-negative double
 };
@@ -44,6 +44,8 @@ struct MarchArgs {
   int32_t level;     // HEALPix level of every input ray (-1: injected rays)
   int32_t spawn;     // 1: input ray r is (src_begin + r/12, pix r%12, s 0, w 0/1)
   int32_t lds_keys_fit;  // 1: flat cell indices fit 32 bits (Gamma staged in LDS)
+  int32_t refill_min;    // idle lanes that trigger a refill of a wavefront
+  int64_t claim;         // rays a wavefront claims at a time
   double h_cm, sigma0, tau_max, s_max, h3;
   double r2split;    // split iff s*s > r2split (this level)
   double sqrt_omega; // sqrt of the pixel solid angle (this level)
@@ -87,6 +89,8 @@ struct nrt_ctx {
   nrt::Layout lay;
   int device;
   int cu_count;
+  int march_blocks_per_cu;  // resident blocks of the march kernel per CU
+  nrt_tuning tuning;        // launch parameters (0 = default)
   hipStream_t stream;
   char* ws;
   // typed views into the workspace
@@ -122,6 +126,7 @@ hipError_t launch_prep(nrt_ctx* c);
 hipError_t launch_zero(double* p, int64_t count, int cus, hipStream_t s);
 hipError_t launch_zero_accum(Accum* acc, hipStream_t s);
 hipError_t launch_march(const nrt_ctx* c, const MarchArgs& a, int64_t rays);
+hipError_t march_blocks_per_cu(bool mixed, int* blocks);
 hipError_t launch_healpix(int level, int64_t first, int64_t count, double* out, hipStream_t s);
 
 // merge.hip

@@ -69,45 +69,52 @@ struct LaneAcc {
   unsigned long long segments = 0;
 };
 
-// Per-block Gamma accumulator in LDS.  The rays of one block are a bundle of
-// neighbouring HEALPix pixels of one source and level (nested pixel order is
-// a Z-order curve and children are queued next to each other), so they cross
-// the same cells several times; deposits are summed in an open-addressing
-// hash table keyed by the cell index and flushed to Gamma with one global
-// atomic per distinct cell.  A deposit that finds no slot within kProbe
-// probes goes straight to global memory.
-constexpr int kSlots = 4096;
+// Per-wavefront Gamma accumulator in LDS.  A wavefront marches rays claimed
+// in runs of kClaim consecutive queue entries; nested HEALPix order is a
+// Z-order curve and children are queued next to each other, so such a run
+// is a bundle of neighbouring pixels of one source and level, and by the
+// split rule it crosses each cell several times.  Deposits are summed in an
+// open-addressing hash table keyed by the cell index and folded into Gamma
+// with one global atomic per distinct cell when the table is half full.  A
+// deposit that finds no slot within kProbe probes goes straight to Gamma.
+constexpr int kWaves = kBlock / 64;
+constexpr int kWaveSlots = 1024;
+constexpr int kFlushAt = kWaveSlots / 2;
 constexpr int kProbe = 16;
+constexpr int kClaim = 256;
 constexpr uint32_t kEmpty = 0xffffffffu;
 
 template <typename V>
-struct DepositTable {
+struct WaveTable {
   uint32_t* key;
   V* val;
   double* gamma;
-  bool on;  // false when cell indices do not fit 32 bits
+  bool on;  // false when flat cell indices do not fit 32 bits
 
-  __device__ __forceinline__ void add(int64_t c, V v) const {
+  // returns true if the deposit occupied a new slot
+  __device__ __forceinline__ bool add(int64_t c, V v) const {
     if (on) {
       const uint32_t k = uint32_t(c);
-      uint32_t h = (k * 2654435761u) >> (32 - 12);
+      uint32_t h = (k * 2654435761u) >> 22;
 #pragma unroll 1
       for (int probe = 0; probe < kProbe; ++probe) {
         const uint32_t old = atomicCAS(&key[h], kEmpty, k);
         if (old == kEmpty || old == k) {
           atomicAdd(&val[h], v);
-          return;
+          return old == kEmpty;
         }
-        h = (h + 1) & (kSlots - 1);
+        h = (h + 1) & (kWaveSlots - 1);
       }
     }
     atomicAdd(gamma + c, double(v));
+    return false;
   }
 
-  // all threads of the block: fold the table into Gamma and clear it
-  __device__ __forceinline__ void flush() const {
-    __syncthreads();
-    for (int q = threadIdx.x; q < kSlots; q += blockDim.x) {
+  // whole wavefront: fold the table into Gamma and clear it (LDS operations
+  // of one wavefront complete in program order)
+  __device__ __forceinline__ void flush(int lane) const {
+    __builtin_amdgcn_wave_barrier();
+    for (int q = lane; q < kWaveSlots; q += 64) {
       const uint32_t k = key[q];
       if (k != kEmpty) {
         atomicAdd(gamma + k, double(val[q]));
@@ -115,312 +122,399 @@ struct DepositTable {
         val[q] = V(0);
       }
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
   }
 };
 
-// March one ray from distance s until it stops.  o: source position, d:
-// unit direction, L: photon rate of the ray, w: tau (FP64) or exp(-tau)
-// (MIXED).  On a split, `split` is set and s_out / w_out carry the state
-// the children start from.  Unwrapped cell coordinates (i) keep the plane
-// crossings exact across periodic wraps; wrapped ones (w) address memory.
+// outcome of a step: keep marching, escaped, truncated, or split
+constexpr int kGoOn = 0, kEscaped = 1, kTruncated = 2, kSplit = 3;
+
+// State of the ray a lane is marching.  Unwrapped cell coordinates (i) keep
+// the plane crossings exact across periodic wraps; wrapped ones (w) address
+// memory.
+struct RayState {
+  double o0, o1, o2, d0, d1, d2;
+  double t0, t1, t2;
+  double s, L;
+  double tau, P;    // FP64 path: optical depth, photons carried
+  double T, absf;   // mixed path: transmitted fraction, absorbed fraction
+  double r2s, sqo;  // split radius^2 and sqrt(pixel solid angle) of the level
+  float s_rate;     // mixed path: L / h^3 in FP32
+  int i0, i1, i2, w0, w1, w2;
+  int st0, st1, st2;
+  int level;
+  uint32_t src, pix;
+};
+
+// Load ray r of the launch (a virtual spawn index, a queue entry or an
+// injected ray) and find its start cell.  Returns kEscaped if it starts
+// outside an open box, else kGoOn.
 template <bool MIXED>
-__device__ void march_ray(const MarchArgs& A, const DepositTable<typename std::conditional<MIXED, float, double>::type>& tab,
-                          double o0, double o1, double o2, double d0,
-                          double d1, double d2, double L, int level, double r2split,
-                          double sqrt_omega, double s, double w, LaneAcc& acc, bool& split,
-                          double& s_out, double& w_out) {
+__device__ int ray_init(RayState& R, const MarchArgs& A, int64_t r) {
+  double w;
+  if (A.level < 0) {  // injected rays: never split
+    R.o0 = A.inj_origin[3 * r];
+    R.o1 = A.inj_origin[3 * r + 1];
+    R.o2 = A.inj_origin[3 * r + 2];
+    R.d0 = A.inj_dir[3 * r];
+    R.d1 = A.inj_dir[3 * r + 1];
+    R.d2 = A.inj_dir[3 * r + 2];
+    R.L = A.inj_L[r];
+    R.level = A.inj_level[r];
+    R.s = 0.0;
+    w = MIXED ? 1.0 : 0.0;
+    R.r2s = __builtin_inf();
+    R.sqo = A.sqrt_omega_tab[R.level];  // by value in the argument block
+    R.src = R.pix = 0;
+  } else {
+    if (A.spawn) {
+      R.src = uint32_t(A.src_begin + r / 12);
+      R.pix = uint32_t(r % 12);
+      R.s = 0.0;
+      w = MIXED ? 1.0 : 0.0;
+    } else {
+      R.src = A.in.src[r];
+      R.pix = A.in.pix[r];
+      R.s = A.in.s[r];
+      w = A.in.w[r];
+    }
+    R.level = A.level;
+    R.o0 = A.src_pos[3 * int64_t(R.src)];
+    R.o1 = A.src_pos[3 * int64_t(R.src) + 1];
+    R.o2 = A.src_pos[3 * int64_t(R.src) + 2];
+    R.L = ldexp(A.src_l0[R.src], -2 * R.level);
+    healpix_dir(R.level, R.pix, R.d0, R.d1, R.d2);
+    R.r2s = A.r2split;
+    R.sqo = A.sqrt_omega;
+  }
+  R.i0 = start_cell(R.o0, R.s, R.d0);
+  R.i1 = start_cell(R.o1, R.s, R.d1);
+  R.i2 = start_cell(R.o2, R.s, R.d2);
+  R.st0 = R.d0 > 0.0 ? 1 : (R.d0 < 0.0 ? -1 : 0);
+  R.st1 = R.d1 > 0.0 ? 1 : (R.d1 < 0.0 ? -1 : 0);
+  R.st2 = R.d2 > 0.0 ? 1 : (R.d2 < 0.0 ? -1 : 0);
+  R.t0 = plane_t(R.o0, R.d0, R.i0);
+  R.t1 = plane_t(R.o1, R.d1, R.i1);
+  R.t2 = plane_t(R.o2, R.d2, R.i2);
+  if (MIXED) {
+    R.T = w;
+    R.absf = 0.0;
+    R.s_rate = float(R.L / A.h3);
+  } else {
+    R.tau = w;
+    R.P = R.L * exp(-R.tau);
+  }
+  const int n = A.n;
+  const bool out = R.i0 < 0 || R.i0 >= n || R.i1 < 0 || R.i1 >= n || R.i2 < 0 || R.i2 >= n;
+  if (!A.periodic && out) return kEscaped;
+  R.w0 = A.periodic ? wrap_cell(R.i0, n) : R.i0;
+  R.w1 = A.periodic ? wrap_cell(R.i1, n) : R.i1;
+  R.w2 = A.periodic ? wrap_cell(R.i2, n) : R.i2;
+  return kGoOn;
+}
+
+
+// Stop tests at the current cell boundary, then one cell segment: optical
+// depth, Eq. lut_eqn deposit with the overlap correction, advance.  The
+// caller books the photons of a ray that stops.  `inserted` counts new table
+// slots taken by this call's deposits.
+template <bool MIXED, typename V>
+__device__ int ray_step(RayState& R, const MarchArgs& A, const WaveTable<V>& tab, LaneAcc& acc,
+                        int& inserted) {
   const int n = A.n;
   const int64_t n64 = n;
   const bool open_box = !A.periodic;
-  int i0 = start_cell(o0, s, d0), i1 = start_cell(o1, s, d1), i2 = start_cell(o2, s, d2);
-  const int st0 = d0 > 0.0 ? 1 : (d0 < 0.0 ? -1 : 0);
-  const int st1 = d1 > 0.0 ? 1 : (d1 < 0.0 ? -1 : 0);
-  const int st2 = d2 > 0.0 ? 1 : (d2 < 0.0 ? -1 : 0);
-  double t0 = plane_t(o0, d0, i0), t1 = plane_t(o1, d1, i1), t2 = plane_t(o2, d2, i2);
-  auto outside = [n](int a, int b, int c) {
-    return a < 0 || a >= n || b < 0 || b >= n || c < 0 || c >= n;
-  };
+  if (A.periodic && R.s >= A.s_max) return kEscaped;
+  if (MIXED ? (R.T <= A.t_min) : (R.tau >= A.tau_max)) return kTruncated;
+  if (R.s * R.s > R.r2s) return R.level >= A.l_max ? kTruncated : kSplit;
+  // next crossing: lowest axis wins exact ties
+  int ax = 0;
+  double tn = R.t0;
+  if (R.t1 < tn) {
+    ax = 1;
+    tn = R.t1;
+  }
+  if (R.t2 < tn) {
+    ax = 2;
+    tn = R.t2;
+  }
+  double ds = tn - R.s;
+  if (ds < 0.0) ds = 0.0;
+  const int64_t c = int64_t(R.w0) + n64 * (int64_t(R.w1) + n64 * int64_t(R.w2));
 
-  // photons carried by the ray: P = L e^{-tau} (FP64), or L * T (MIXED)
-  double tau = 0.0, P = 0.0, T = 0.0, absorbed_frac = 0.0;
-  float s_rate = 0.0f;  // L / h^3 in FP32 (MIXED)
+  // ---- segment physics (Eq. lut_eqn, Eq. optical_depth) ----
+  double G64 = 0.0, a64 = 0.0;
+  float G32 = 0.0f, a32 = 0.0f;
   if (MIXED) {
-    T = w;
-    s_rate = float(L / A.h3);
+    a32 = fabsf(A.a32[c]);
+    const float dsf = float(ds);
+    const float dtau = A.kf * a32 * dsf;
+    const float em = -expm1f(-dtau);  // absorbed share of the entering photons
+    // transmitted fraction in FP64: the absorbed part for weak absorption,
+    // the surviving part for strong absorption (where em rounds towards 1)
+    double dT, Tn;
+    if (em < 0.5f) {
+      dT = R.T * double(em);
+      Tn = R.T - dT;
+    } else {
+      Tn = R.T * double(expf(-dtau));
+      dT = R.T - Tn;
+    }
+    const float Tf = float(R.T);
+    R.T = Tn;
+    R.absf += dT;
+    G32 = a32 > 0.0f ? (R.s_rate * float(dT)) / a32 : R.s_rate * Tf * (A.kf * dsf);
   } else {
-    tau = w;
-    P = L * exp(-tau);
+    a64 = fabs(A.a64[c]);
+    const double dl = ds * A.h_cm;
+    const double dtau = A.sigma0 * a64 * dl;
+    const double dN = R.P * (-expm1(-dtau));
+    G64 = a64 > 0.0 ? dN / (a64 * A.h3) : R.P * A.sigma0 * dl / A.h3;
+    acc.absorbed += dN;
+    R.P -= dN;
+    R.tau += dtau;
   }
-  if (open_box && outside(i0, i1, i2)) {
-    acc.escaped += MIXED ? L * T : P;
-    return;
-  }
-  int w0 = open_box ? i0 : wrap_cell(i0, n);
-  int w1 = open_box ? i1 : wrap_cell(i1, n);
-  int w2 = open_box ? i2 : wrap_cell(i2, n);
 
-  for (;;) {
-    if (A.periodic && s >= A.s_max) {
-      acc.escaped += MIXED ? L * T : P;
-      break;
+  // ---- overlap correction (Eqs. correction .. new_secondary) ----
+  double fc = 1.0;
+  bool secondary = false;
+  int64_t c2 = 0;
+  double a2_64 = 0.0;
+  float a2_32 = 0.0f;
+  if (A.corr != NRT_CORR_NONE) {
+    const double rm = 0.5 * (R.s + tn);
+    const double lpix = rm * R.sqo;
+    // distance from the segment midpoint to the nearest face of the cell
+    double dedge;
+    int fax = 0, fdir;
+    {
+      const double m0 = R.o0 + rm * R.d0;
+      const double dm = m0 - double(R.i0), dp = double(R.i0 + 1) - m0;
+      dedge = dm < dp ? dm : dp;
+      fdir = dm < dp ? -1 : (dp < dm ? 1 : (R.d0 < 0.0 ? -1 : 1));
     }
-    if (MIXED ? (T <= A.t_min) : (tau >= A.tau_max)) {
-      acc.truncated += MIXED ? L * T : P;
-      break;
-    }
-    if (s * s > r2split) {
-      if (level >= A.l_max) {
-        acc.truncated += MIXED ? L * T : P;
-        break;
-      }
-      split = true;
-      s_out = s;
-      w_out = MIXED ? T : tau;
-      break;
-    }
-    // next crossing: lowest axis wins exact ties
-    int ax = 0;
-    double tn = t0;
-    if (t1 < tn) {
-      ax = 1;
-      tn = t1;
-    }
-    if (t2 < tn) {
-      ax = 2;
-      tn = t2;
-    }
-    double ds = tn - s;
-    if (ds < 0.0) ds = 0.0;
-    const int64_t c = int64_t(w0) + n64 * (int64_t(w1) + n64 * int64_t(w2));
-
-    // ---- segment physics (Eq. lut_eqn, Eq. optical_depth) ----
-    double G64 = 0.0, a64 = 0.0;
-    float G32 = 0.0f, a32 = 0.0f;
-    if (MIXED) {
-      a32 = fabsf(A.a32[c]);
-      const float dsf = float(ds);
-      const float dtau = A.kf * a32 * dsf;
-      const float em = -expm1f(-dtau);
-      const float Tf = float(T);
-      const float dT = Tf * em;
-      T -= double(dT);
-      absorbed_frac += double(dT);
-      G32 = a32 > 0.0f ? (s_rate * dT) / a32 : s_rate * Tf * (A.kf * dsf);
-    } else {
-      a64 = fabs(A.a64[c]);
-      const double dl = ds * A.h_cm;
-      const double dtau = A.sigma0 * a64 * dl;
-      const double dN = P * (-expm1(-dtau));
-      G64 = a64 > 0.0 ? dN / (a64 * A.h3) : P * A.sigma0 * dl / A.h3;
-      acc.absorbed += dN;
-      P -= dN;
-      tau += dtau;
-    }
-
-    // ---- overlap correction (Eqs. correction .. new_secondary) ----
-    double fc = 1.0;
-    bool secondary = false;
-    int64_t c2 = 0;
-    double a2_64 = 0.0;
-    float a2_32 = 0.0f;
-    if (A.corr != NRT_CORR_NONE) {
-      const double rm = 0.5 * (s + tn);
-      const double lpix = rm * sqrt_omega;
-      // distances from the segment midpoint to the faces of the cell
-      double dedge = __builtin_inf();
-      int fax = 0, fdir = 1;
-      {
-        const double m0 = o0 + rm * d0;
-        const double dm = m0 - double(i0), dp = double(i0 + 1) - m0;
-        const double da = dm < dp ? dm : dp;
-        const int sa = dm < dp ? -1 : (dp < dm ? 1 : (d0 < 0.0 ? -1 : 1));
+    {
+      const double m1 = R.o1 + rm * R.d1;
+      const double dm = m1 - double(R.i1), dp = double(R.i1 + 1) - m1;
+      const double da = dm < dp ? dm : dp;
+      if (da < dedge) {
         dedge = da;
-        fdir = sa;
+        fax = 1;
+        fdir = dm < dp ? -1 : (dp < dm ? 1 : (R.d1 < 0.0 ? -1 : 1));
       }
-      {
-        const double m1 = o1 + rm * d1;
-        const double dm = m1 - double(i1), dp = double(i1 + 1) - m1;
-        const double da = dm < dp ? dm : dp;
-        const int sa = dm < dp ? -1 : (dp < dm ? 1 : (d1 < 0.0 ? -1 : 1));
-        if (da < dedge) {
-          dedge = da;
-          fax = 1;
-          fdir = sa;
+    }
+    {
+      const double m2 = R.o2 + rm * R.d2;
+      const double dm = m2 - double(R.i2), dp = double(R.i2 + 1) - m2;
+      const double da = dm < dp ? dm : dp;
+      if (da < dedge) {
+        dedge = da;
+        fax = 2;
+        fdir = dm < dp ? -1 : (dp < dm ? 1 : (R.d2 < 0.0 ? -1 : 1));
+      }
+    }
+    if (dedge < 0.5 * lpix) {
+      const double f = 0.5 + dedge / lpix;
+      if (A.corr == NRT_CORR_LINEAR) {
+        fc = f;
+      } else if (A.corr == NRT_CORR_SQUARED) {
+        fc = f * f;
+      } else {
+        bool usable = false;
+        const int j0 = R.i0 + (fax == 0 ? fdir : 0);
+        const int j1 = R.i1 + (fax == 1 ? fdir : 0);
+        const int j2 = R.i2 + (fax == 2 ? fdir : 0);
+        const bool j_out = j0 < 0 || j0 >= n || j1 < 0 || j1 >= n || j2 < 0 || j2 >= n;
+        if (!open_box || !j_out) {
+          const int v0 = fax == 0 ? (open_box ? j0 : wrap_step(R.w0, fdir, n)) : R.w0;
+          const int v1 = fax == 1 ? (open_box ? j1 : wrap_step(R.w1, fdir, n)) : R.w1;
+          const int v2 = fax == 2 ? (open_box ? j2 : wrap_step(R.w2, fdir, n)) : R.w2;
+          c2 = int64_t(v0) + n64 * (int64_t(v1) + n64 * int64_t(v2));
+          if (MIXED) {
+            const float raw = A.a32[c2];
+            usable = !__builtin_signbit(raw);
+            a2_32 = raw;
+          } else {
+            const double raw = A.a64[c2];
+            usable = !__builtin_signbit(raw);
+            a2_64 = raw;
+          }
         }
-      }
-      {
-        const double m2 = o2 + rm * d2;
-        const double dm = m2 - double(i2), dp = double(i2 + 1) - m2;
-        const double da = dm < dp ? dm : dp;
-        const int sa = dm < dp ? -1 : (dp < dm ? 1 : (d2 < 0.0 ? -1 : 1));
-        if (da < dedge) {
-          dedge = da;
-          fax = 2;
-          fdir = sa;
-        }
-      }
-      if (dedge < 0.5 * lpix) {
-        const double f = 0.5 + dedge / lpix;
-        if (A.corr == NRT_CORR_LINEAR) {
+        if (A.corr == NRT_CORR_CONSERVATIVE) {
+          if (usable) fc = f;
+        } else {  // NAIVE
           fc = f;
-        } else if (A.corr == NRT_CORR_SQUARED) {
-          fc = f * f;
-        } else {
-          bool usable = false;
-          const int j0 = i0 + (fax == 0 ? fdir : 0);
-          const int j1 = i1 + (fax == 1 ? fdir : 0);
-          const int j2 = i2 + (fax == 2 ? fdir : 0);
-          if (!open_box || !outside(j0, j1, j2)) {
-            const int v0 = fax == 0 ? (open_box ? j0 : wrap_step(w0, fdir, n)) : w0;
-            const int v1 = fax == 1 ? (open_box ? j1 : wrap_step(w1, fdir, n)) : w1;
-            const int v2 = fax == 2 ? (open_box ? j2 : wrap_step(w2, fdir, n)) : w2;
-            c2 = int64_t(v0) + n64 * (int64_t(v1) + n64 * int64_t(v2));
-            if (MIXED) {
-              const float raw = A.a32[c2];
-              usable = !__builtin_signbit(raw);
-              a2_32 = raw;
-            } else {
-              const double raw = A.a64[c2];
-              usable = !__builtin_signbit(raw);
-              a2_64 = raw;
-            }
-          }
-          if (A.corr == NRT_CORR_CONSERVATIVE) {
-            if (usable) fc = f;
-          } else {  // NAIVE
-            fc = f;
-          }
-          secondary = usable;
         }
+        secondary = usable;
       }
-    }
-
-    // ---- deposit ----
-    if constexpr (MIXED) {
-      const float fcf = float(fc);
-      tab.add(c, fcf * G32);
-      if (secondary) tab.add(c2, ((1.0f - fcf) * (a32 / a2_32)) * G32);
-    } else {
-      tab.add(c, fc * G64);
-      if (secondary) tab.add(c2, ((1.0 - fc) * (a64 / a2_64)) * G64);
-    }
-
-    // ---- advance one cell ----
-    s = tn;
-    if (ax == 0) {
-      i0 += st0;
-      w0 = open_box ? i0 : wrap_step(w0, st0, n);
-      t0 = plane_t(o0, d0, i0);
-    } else if (ax == 1) {
-      i1 += st1;
-      w1 = open_box ? i1 : wrap_step(w1, st1, n);
-      t1 = plane_t(o1, d1, i1);
-    } else {
-      i2 += st2;
-      w2 = open_box ? i2 : wrap_step(w2, st2, n);
-      t2 = plane_t(o2, d2, i2);
-    }
-    acc.segments += 1;
-    if (open_box && outside(i0, i1, i2)) {
-      acc.escaped += MIXED ? L * T : P;
-      break;
     }
   }
-  if (MIXED) acc.absorbed += L * absorbed_frac;
+
+  // ---- deposit ----
+  if constexpr (MIXED) {
+    const float fcf = float(fc);
+    inserted += tab.add(c, fcf * G32) ? 1 : 0;
+    if (secondary) inserted += tab.add(c2, ((1.0f - fcf) * (a32 / a2_32)) * G32) ? 1 : 0;
+  } else {
+    inserted += tab.add(c, fc * G64) ? 1 : 0;
+    if (secondary) inserted += tab.add(c2, ((1.0 - fc) * (a64 / a2_64)) * G64) ? 1 : 0;
+  }
+
+  // ---- advance one cell ----
+  R.s = tn;
+  if (ax == 0) {
+    R.i0 += R.st0;
+    R.w0 = open_box ? R.i0 : wrap_step(R.w0, R.st0, n);
+    R.t0 = plane_t(R.o0, R.d0, R.i0);
+  } else if (ax == 1) {
+    R.i1 += R.st1;
+    R.w1 = open_box ? R.i1 : wrap_step(R.w1, R.st1, n);
+    R.t1 = plane_t(R.o1, R.d1, R.i1);
+  } else {
+    R.i2 += R.st2;
+    R.w2 = open_box ? R.i2 : wrap_step(R.w2, R.st2, n);
+    R.t2 = plane_t(R.o2, R.d2, R.i2);
+  }
+  acc.segments += 1;
+  if (open_box &&
+      (R.i0 < 0 || R.i0 >= n || R.i1 < 0 || R.i1 >= n || R.i2 < 0 || R.i2 >= n))
+    return kEscaped;
+  return kGoOn;
 }
 
+// Whole wavefront: append the four children of every lane with a pending
+// split to the next level's queue (one atomicAdd for the wavefront).
+__device__ __forceinline__ void push_pending(unsigned long long* count, const RayQueue& out,
+                                             int64_t out_cap, unsigned long long* overflow,
+                                             int lane, bool& pend, uint32_t p_src,
+                                             uint32_t p_pix, double p_s, double p_w) {
+  const uint64_t pm = __ballot(pend);
+  if (!pm) return;
+  const int leader = __builtin_ctzll(pm);
+  unsigned long long slot0 = 0;
+  if (lane == leader) slot0 = atomicAdd(count, 4ull * static_cast<unsigned long long>(__popcll(pm)));
+  slot0 = read_lane64(slot0, leader);
+  if (pend) {
+    const unsigned long long slot = slot0 + 4ull * lanes_below(pm);
+    if (slot + 4 <= static_cast<unsigned long long>(out_cap)) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        out.src[slot + k] = p_src;
+        out.pix[slot + k] = 4u * p_pix + uint32_t(k);
+        out.s[slot + k] = p_s;
+        out.w[slot + k] = p_w;
+      }
+    } else {
+      atomicAdd(overflow, 1ull);
+    }
+    pend = false;
+  }
+}
+
+// Persistent march: every wavefront claims runs of A.claim rays of the
+// launch's range, refills idle lanes from its run once A.refill_min of them
+// are idle, advances every busy lane by one cell per step, and folds its LDS
+// table into Gamma when half full.  A lane whose ray splits keeps the
+// children's start state in registers; the wavefront appends the children of
+// all pending splits to the next level's queue with one atomicAdd once 32 are
+// pending (or a pending lane splits again, or the run ends).
 template <bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_march(MarchArgs A) {
   using V = typename std::conditional<MIXED, float, double>::type;
-  // the deposit table, reused for the budget reduction at the end
-  __shared__ __align__(16) unsigned char lds[kSlots * (sizeof(uint32_t) + sizeof(V))];
-  uint32_t* lds_key = reinterpret_cast<uint32_t*>(lds);
-  V* lds_val = reinterpret_cast<V*>(lds + kSlots * sizeof(uint32_t));
-  const DepositTable<V> tab{lds_key, lds_val, A.gamma, A.lds_keys_fit != 0};
-  for (int q = threadIdx.x; q < kSlots; q += kBlock) {
-    lds_key[q] = kEmpty;
-    lds_val[q] = V(0);
-  }
-  __syncthreads();
-  LaneAcc acc;
+  // per-wavefront deposit tables, reused for the budget reduction at the end
+  __shared__ __align__(16) unsigned char lds[kWaves * kWaveSlots * (sizeof(uint32_t) + sizeof(V))];
+  const int wave = threadIdx.x >> 6;
   const int lane = __lane_id();
-  const int64_t stride = int64_t(gridDim.x) * kBlock;
-  for (int64_t base = A.begin + int64_t(blockIdx.x) * kBlock; base < A.end; base += stride) {
-    const int64_t r = base + threadIdx.x;
-    bool split = false;
-    uint32_t src = 0, pix = 0;
-    double s_out = 0.0, w_out = 0.0;
-    if (r < A.end) {
-      double o0, o1, o2, d0, d1, d2, L, s, w, r2s, sqo;
-      int level;
-      if (A.level < 0) {  // injected rays: never split
-        o0 = A.inj_origin[3 * r];
-        o1 = A.inj_origin[3 * r + 1];
-        o2 = A.inj_origin[3 * r + 2];
-        d0 = A.inj_dir[3 * r];
-        d1 = A.inj_dir[3 * r + 1];
-        d2 = A.inj_dir[3 * r + 2];
-        L = A.inj_L[r];
-        level = A.inj_level[r];
-        s = 0.0;
-        w = MIXED ? 1.0 : 0.0;
-        r2s = __builtin_inf();
-        sqo = A.sqrt_omega_tab[level];  // by value in the argument block
-      } else {
-        if (A.spawn) {
-          src = uint32_t(A.src_begin + r / 12);
-          pix = uint32_t(r % 12);
-          s = 0.0;
-          w = MIXED ? 1.0 : 0.0;
+  uint32_t* key = reinterpret_cast<uint32_t*>(lds) + wave * kWaveSlots;
+  V* val = reinterpret_cast<V*>(lds + kWaves * kWaveSlots * sizeof(uint32_t)) + wave * kWaveSlots;
+  const WaveTable<V> tab{key, val, A.gamma, A.lds_keys_fit != 0};
+  for (int q = lane; q < kWaveSlots; q += 64) {
+    key[q] = kEmpty;
+    val[q] = V(0);
+  }
+  __builtin_amdgcn_wave_barrier();
+
+  LaneAcc acc;
+  RayState R;
+  bool busy = false;
+  // pending split of this lane: children start state
+  bool pend = false;
+  uint32_t p_src = 0, p_pix = 0;
+  double p_s = 0.0, p_w = 0.0;
+  const int64_t total = A.end - A.begin;
+  const int64_t claim = A.claim;
+  int64_t pool = 0, pool_end = 0;  // wavefront-uniform run of claimed rays
+  bool exhausted = total <= 0;
+  int fill = 0;                    // wavefront-uniform occupied table slots
+  for (;;) {
+    const uint64_t idle = __ballot(!busy);
+    const int n_idle = __popcll(idle);
+    if (!exhausted && (n_idle >= A.refill_min || n_idle == 64)) {
+      if (pool == pool_end) {
+        unsigned long long b = 0;
+        if (lane == 0) b = atomicAdd(&A.acc->claim, static_cast<unsigned long long>(claim));
+        b = read_lane64(b, 0);
+        if (int64_t(b) >= total) {
+          exhausted = true;
         } else {
-          src = A.in.src[r];
-          pix = A.in.pix[r];
-          s = A.in.s[r];
-          w = A.in.w[r];
+          pool = int64_t(b);
+          pool_end = int64_t(b) + claim < total ? int64_t(b) + claim : total;
         }
-        level = A.level;
-        o0 = A.src_pos[3 * int64_t(src)];
-        o1 = A.src_pos[3 * int64_t(src) + 1];
-        o2 = A.src_pos[3 * int64_t(src) + 2];
-        L = ldexp(A.src_l0[src], -2 * level);
-        healpix_dir(level, pix, d0, d1, d2);
-        r2s = A.r2split;
-        sqo = A.sqrt_omega;
       }
-      march_ray<MIXED>(A, tab, o0, o1, o2, d0, d1, d2, L, level, r2s, sqo, s, w, acc, split,
-                       s_out, w_out);
+      if (!exhausted) {
+        const int64_t avail = pool_end - pool;
+        const unsigned rank = lanes_below(idle);
+        if (!busy && int64_t(rank) < avail) {
+          const int start = ray_init<MIXED>(R, A, A.begin + pool + rank);
+          busy = start == kGoOn;
+          if (!busy) acc.escaped += MIXED ? R.L * R.T : R.P;
+        }
+        pool += int64_t(n_idle) < avail ? int64_t(n_idle) : avail;
+      }
     }
-    tab.flush();
-    // children of the rays that split: one allocation per wavefront
-    const uint64_t mask = __ballot(split);
-    if (mask) {
-      const int leader = __builtin_ctzll(mask);
-      unsigned long long slot0 = 0;
-      if (lane == leader)
-        slot0 = atomicAdd(&A.acc->out_count[A.level + 1],
-                          4ull * static_cast<unsigned long long>(__popcll(mask)));
-      slot0 = read_lane64(slot0, leader);
-      if (split) {
-        const unsigned long long slot = slot0 + 4ull * lanes_below(mask);
-        if (slot + 4 <= static_cast<unsigned long long>(A.out_cap)) {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            A.out.src[slot + k] = src;
-            A.out.pix[slot + k] = 4u * pix + uint32_t(k);
-            A.out.s[slot + k] = s_out;
-            A.out.w[slot + k] = w_out;
-          }
-        } else {
-          atomicAdd(&A.acc->overflow, 1ull);
-        }
+    if (__ballot(busy) == 0) {
+      if (exhausted) break;
+      continue;
+    }
+    int code = kGoOn, inserted = 0;
+    if (busy) {
+      code = ray_step<MIXED>(R, A, tab, acc, inserted);
+      if (code != kGoOn) {
+        busy = false;
+        const double carried = MIXED ? R.L * R.T : R.P;
+        acc.escaped += code == kEscaped ? carried : 0.0;
+        acc.truncated += code == kTruncated ? carried : 0.0;
+        if (MIXED) acc.absorbed += R.L * R.absf;
       }
+    }
+    fill += __popcll(__ballot(inserted >= 1)) + __popcll(__ballot(inserted >= 2));
+    const bool splits = code == kSplit;
+    if (__ballot(splits && pend))  // a lane splits again
+      push_pending(&A.acc->out_count[A.level + 1], A.out, A.out_cap, &A.acc->overflow, lane, pend,
+                   p_src, p_pix, p_s, p_w);
+    if (splits) {
+      pend = true;
+      p_src = R.src;
+      p_pix = R.pix;
+      p_s = R.s;
+      p_w = MIXED ? R.T : R.tau;
+    }
+    if (__popcll(__ballot(pend)) >= 32)
+      push_pending(&A.acc->out_count[A.level + 1], A.out, A.out_cap, &A.acc->overflow, lane, pend,
+                   p_src, p_pix, p_s, p_w);
+    if (fill >= kFlushAt) {
+      tab.flush(lane);
+      fill = 0;
     }
   }
+  push_pending(&A.acc->out_count[A.level + 1], A.out, A.out_cap, &A.acc->overflow, lane, pend,
+               p_src, p_pix, p_s, p_w);
+  tab.flush(lane);
 
   // block reduction of the lane budgets, then one atomic per block and term
-  // (the deposit table is empty after its last flush)
-  static_assert(kSlots * (sizeof(uint32_t) + sizeof(V)) >= kBlock * 32, "reduction space");
+  __syncthreads();
+  static_assert(kWaves * kWaveSlots * (sizeof(uint32_t) + sizeof(V)) >= kBlock * 32,
+                "reduction space");
   double(*red_d)[kBlock] = reinterpret_cast<double(*)[kBlock]>(lds);
   unsigned long long* red_u = reinterpret_cast<unsigned long long*>(lds + 3 * kBlock * 8);
   red_d[0][threadIdx.x] = acc.absorbed;
@@ -518,8 +612,23 @@ hipError_t launch_zero_accum(Accum* acc, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_march(const nrt_ctx* c, const MarchArgs& a, int64_t rays) {
-  const int blocks = grid_for(rays, kBlock, c->cu_count * 8);
+hipError_t march_blocks_per_cu(bool mixed, int* blocks) {
+  return mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_march<true>, kBlock, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_march<false>, kBlock, 0);
+}
+
+// persistent grid: as many blocks as stay resident, or fewer for small launches
+hipError_t launch_march(const nrt_ctx* c, const MarchArgs& args, int64_t rays) {
+  int per_cu = c->march_blocks_per_cu > 0 ? c->march_blocks_per_cu : 2;
+  if (c->tuning.blocks_per_cu > 0 && c->tuning.blocks_per_cu < per_cu)
+    per_cu = c->tuning.blocks_per_cu;
+  const int blocks = grid_for(rays, kBlock, c->cu_count * per_cu);
+  MarchArgs a = args;
+  // defaults from a sweep on the 128^3 lognormal workload: one wavefront of
+  // rays per claim balances best; a refill once 16 lanes idle amortizes the
+  // ray set-up
+  a.claim = c->tuning.claim > 0 ? c->tuning.claim : 64;
+  a.refill_min = c->tuning.refill_min > 0 ? c->tuning.refill_min : 16;
   if (c->desc.precision == NRT_MIXED)
     hipLaunchKernelGGL(k_march<true>, dim3(blocks), dim3(kBlock), 0, c->stream, a);
   else

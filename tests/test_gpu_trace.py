@@ -249,3 +249,31 @@ def test_rt_step_stromgren(gpu, orc):
         r_a = r_s * (1 - math.exp(-step * dt / t_rec)) ** (1 / 3)
         assert r_n / r_a == pytest.approx(1.0, abs=0.02)
     ctx.destroy()
+
+
+@pytest.mark.slow
+def test_bubbles_256_4096_sources(gpu, orc):
+    """The 256^3 workload with 4096 sources in their own ionized bubbles, at
+    full size in the benchmark's launch configuration: the mixed path against
+    the FP64 path everywhere; both against the oracle on a seeded subset of 64
+    sources (Gamma is additive over sources for a fixed ionization field)."""
+    w = W.config3()
+    kw = dict(periodic=w.periodic, n_min_ray=w.n_min_ray, l_max=w.l_max, tau_max=w.tau_max,
+              n_th=w.n_th)
+    g64, b64 = run_gpu(gpu, w.n, w.h_cm, w.n_H, w.x, w.pos, w.ndot, 0, cap=1 << 23, **kw)
+    gmx, bmx = run_gpu(gpu, w.n, w.h_cm, w.n_H, w.x, w.pos, w.ndot, 1, cap=1 << 23, **kw)
+    assert max(b64["rays_per_level"]) > (1 << 23) // 4  # exercises the chunked levels
+    assert rel_err(gmx, g64)[0] <= 1e-4
+    assert budget_err(bmx, b64) <= 1e-6
+    for k in ("segments", "rays", "splits"):
+        assert abs(bmx[k] - b64[k]) <= 1e-4 * b64[k]
+    E = b64["emitted"]
+    assert abs(b64["absorbed"] + b64["escaped"] + b64["truncated"] - E) <= 1e-12 * E
+    s = W.subset(w, 64)
+    ref, rb = orc.trace(orc.make_params(w.n, w.h_cm, **kw), w.n_H, w.x, s.pos, s.ndot)
+    gs, bs = run_gpu(gpu, w.n, w.h_cm, w.n_H, w.x, s.pos, s.ndot, 0, **kw)
+    assert rel_err(gs, ref)[0] <= 1e-10
+    assert bs["segments"] == rb["segments"] and bs["splits"] == rb["splits"]
+    gm, bm = run_gpu(gpu, w.n, w.h_cm, w.n_H, w.x, s.pos, s.ndot, 1, **kw)
+    assert rel_err(gm, ref)[0] <= 1e-4
+    assert budget_err(bm, rb) <= 1e-6
