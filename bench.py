@@ -44,13 +44,14 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def run_path(nrt, w, precision, steps, warmup, capacity):
+def run_path(nrt, w, precision, steps, warmup, capacity, graph=0):
     import torch
     desc = nrt.make_desc(w.n, w.h_cm, periodic=w.periodic, n_min_ray=w.n_min_ray, l_max=w.l_max,
                          tau_max=w.tau_max, n_th=w.n_th, precision=precision)
     ctx = nrt.init_grid(desc, w.n_H, w.x, device="cuda:0", max_sources=len(w.ndot),
                         ray_capacity=capacity)
     ctx.add_sources(w.pos, w.ndot)
+    ctx.set_tuning(graph=graph)
     gamma = torch.empty((w.n,) * 3, dtype=torch.float64, device="cuda:0")
     for _ in range(warmup):
         _, b = ctx.trace_step(gamma)
@@ -65,22 +66,107 @@ def run_path(nrt, w, precision, steps, warmup, capacity):
         segs += b["segments"]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    graph = ctx.last_pass_was_graph()
     ctx.destroy()
     return dict(wall_s=wall, ms_per_step=1e3 * wall / steps, segments_per_step=segs // steps,
                 segments_per_s=segs / wall, kernel_ms_total=kernel_ms, launches=launches,
-                avg_launch_ms=kernel_ms / max(launches, 1), budget=b)
+                avg_launch_ms=kernel_ms / max(launches, 1), budget=b, graph=graph)
 
 
-def roofline(path, res):
+def roofline(path, res, counters=None):
     """Per launch: the algorithmic bytes of the segments one march launch
     processes over the launch's duration (HIP events on the library's
     stream); averaged over the timed launches this is bytes per segment times
-    segments over the summed launch time."""
+    segments over the summed launch time.  `traffic`: HBM bytes per launch
+    from the committed counter summary of the same kernel, else None."""
     achieved = BYTES_PER_SEGMENT[path] * res["segments_per_s_kernel"] / 1e9
+    traffic = None
+    mode = "graph" if res.get("graph") else "host"
+    if counters and counters.get("mode") == mode and f"{path}_traffic_bytes_per_launch" in counters:
+        traffic = float(counters[f"{path}_traffic_bytes_per_launch"])
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "k_march", "bytes_per_segment": BYTES_PER_SEGMENT[path],
             "avg_launch_ms": round(res["avg_launch_ms"], 4), "launches": res["launches"]}
+
+
+KERNEL_SOURCES = ["paper_2512_12466_amd/csrc/trace.hip", "paper_2512_12466_amd/csrc/healpix.h",
+                  "paper_2512_12466_amd/csrc/internal.h"]
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_march_counters_lognormal-128-64src.txt")
+LEVELS_PER_PASS = 10  # march launches of one replayed pass of lognormal-128-64src (l_max 9)
+
+
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_counters():
+    """HBM bytes per march launch from the committed counter summary, or None
+    if the march kernel's sources changed since the counters were taken."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    kv = {}
+    for line in open(COUNTERS_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_sha") != kernel_hash():
+        return None
+    return kv
+
+
+def summarize_counters(d, out):
+    """Summarize two rocprofv3 --pmc runs of `bench.py --calibrate-copy 1024`
+    (FETCH_SIZE in fetch_counter_collection.csv, WRITE_SIZE in
+    write_counter_collection.csv): each counter is scaled by what it reads
+    for the calibration copies of known size, then averaged per launch."""
+    import csv
+    import collections
+
+    def load(name):
+        # per path, keep the dispatches of the last pass (the timed replay)
+        rows = collections.defaultdict(dict)
+        for r in csv.DictReader(open(os.path.join(d, name))):
+            k = r["Kernel_Name"]
+            key = ("mixed" if "k_march<true>" in k else "fp64" if "k_march<false>" in k
+                   else "copy" if "copyBuffer" in k else None)
+            if key:
+                did = int(r["Dispatch_Id"])
+                rows[key][did] = rows[key].get(did, 0.0) + float(r["Counter_Value"]) * 1024.0
+        agg = {}
+        for key, per in rows.items():
+            ids = sorted(per)
+            if key != "copy":
+                ids = ids[-(LEVELS_PER_PASS):]
+            agg[key] = [sum(per[i] for i in ids), set(ids)]
+        return agg
+    fetch, write = load("fetch_counter_collection.csv"), load("write_counter_collection.csv")
+    copy_bytes = 3 * 1024 * 2 ** 20  # three 1024 MiB copies read and write this much
+    ff = fetch["copy"][0] / copy_bytes
+    fw = write["copy"][0] / copy_bytes
+    lines = [f"# HBM traffic of k_march from FETCH_SIZE / WRITE_SIZE counter runs",
+             f"# command: rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv "
+             f"-d <dir> -o fetch|write -- python3 bench.py --steps 1 --warmup 1 "
+             f"--no-cpu-baseline --calibrate-copy 1024",
+             f"# summarized with: python bench.py --summarize-counters <dir>",
+             f"# the timed step replays the captured pass (the warm-up pass is host-driven)",
+             f"kernel_sha = {kernel_hash()}",
+             f"mode = graph",
+             f"copy_factor_fetch = {ff:.4f}", f"copy_factor_write = {fw:.4f}"]
+    for path in ("mixed", "fp64"):
+        nf, nw = len(fetch[path][1]), len(write[path][1])
+        fb = fetch[path][0] / ff / max(nf, 1)
+        wb = write[path][0] / fw / max(nw, 1)
+        lines += [f"{path}_fetch_bytes_per_launch = {fb:.1f}",
+                  f"{path}_write_bytes_per_launch = {wb:.1f}",
+                  f"{path}_traffic_bytes_per_launch = {fb + wb:.1f}",
+                  f"{path}_launches = {nf}"]
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def cpu_baseline(w, sources, threads):
@@ -108,10 +194,17 @@ def main():
     ap.add_argument("--paths", default="mixed,fp64")
     ap.add_argument("--cpu-sources", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", type=int, default=0, choices=(0, 1, 2),
+                    help="0: replay the captured pass once eligible (default), 1: never, 2: always")
+    ap.add_argument("--summarize-counters", metavar="DIR",
+                    help="write the counter summary of a profiler output directory and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a kernel of known "
                          "traffic for scaling hardware byte counters)")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, COUNTERS_FILE)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path "
               f"(--gpus {args.gpus} requested)", file=sys.stderr)
@@ -133,16 +226,18 @@ def main():
     res = {}
     for path in args.paths.split(","):
         prec = nrt.MIXED if path == "mixed" else nrt.FP64
-        r = run_path(nrt, w, prec, args.steps, args.warmup, args.capacity)
+        r = run_path(nrt, w, prec, args.steps, args.warmup, args.capacity, args.graph)
         r["segments_per_s_kernel"] = r["segments_per_step"] * args.steps / (
             r["kernel_ms_total"] / 1e3)
         res[path] = r
         log(f"[{path}] {r['ms_per_step']:.2f} ms/step, {r['segments_per_step']} segments, "
             f"{r['segments_per_s'] / 1e9:.3f} Gseg/s wall, "
             f"{r['segments_per_s_kernel'] / 1e9:.3f} Gseg/s in march kernels "
-            f"({r['launches'] // args.steps} launches/step)")
+            f"({r['launches'] // args.steps} launches/step, "
+            f"{'graph replay' if r['graph'] else 'host-driven'})")
     head = "mixed" if "mixed" in res else next(iter(res))
     h = res[head]
+    counters = read_counters()
     out = {
         "metric": METRIC, "value": round(h["segments_per_s"], 1), "unit": "ray-segments/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -151,8 +246,9 @@ def main():
         "dtype": "f32" if head == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "sources": int(len(w.ndot)),
                    "periodic": bool(w.periodic), "n_min_ray": w.n_min_ray, "l_max": w.l_max,
-                   "tau_max": w.tau_max, "path": head, "decisions": "f64"},
-        "roofline": roofline(head, h),
+                   "tau_max": w.tau_max, "path": head, "decisions": "f64",
+                   "graph": bool(h["graph"])},
+        "roofline": roofline(head, h, counters),
     }
     for path, r in res.items():
         if path == head:
@@ -160,7 +256,7 @@ def main():
         out[f"{path}_path"] = {"value": round(r["segments_per_s"], 1), "unit": "ray-segments/s",
                                "ms_per_step": round(r["ms_per_step"], 3),
                                "dtype": "f64" if path == "fp64" else "f32",
-                               "roofline": roofline(path, r)}
+                               "roofline": roofline(path, r, counters)}
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sources, threads)

@@ -191,6 +191,9 @@ typedef struct {
   int32_t refill_min;    /* idle lanes that make a wavefront fetch new rays (1..64) */
   int32_t claim;         /* rays a wavefront claims at a time (64..65536, multiple of 64) */
   int32_t blocks_per_cu; /* resident 256-thread blocks per compute unit               */
+  int32_t graph;         /* 0: replay a captured device-driven pass (hipGraph) once a
+                            pass has shown that every HEALPix level fits its queue;
+                            1: never; 2: always try (falls back on overflow)        */
 } nrt_tuning;
 
 /* Set (or read back) the march launch parameters of a context.  Results
@@ -204,10 +207,13 @@ nrt_status nrt_get_tuning(const nrt_ctx* ctx, nrt_tuning* t);
    each candidate (>= 1).  Uses the context's current grid and sources. */
 nrt_status nrt_autotune(nrt_ctx* ctx, double* gamma_scratch, int32_t passes, nrt_tuning* best);
 
-/* Average duration [ms] of the march kernel launches of the last
-   nrt_trace_step, timed with HIP events on the context's stream, and the
-   number of those launches. */
-nrt_status nrt_last_kernel_time(const nrt_ctx* ctx, double* march_ms, int32_t* launches);
+/* Average duration [ms] of the march kernel launches of the last pass,
+   timed with HIP events on the context's stream, the number of those
+   launches, and whether the pass replayed the captured graph (then the
+   average is the graph's duration over its march launches).  Any pointer
+   may be NULL. */
+nrt_status nrt_last_kernel_time(const nrt_ctx* ctx, double* march_ms, int32_t* launches,
+                                int32_t* graph_replayed);
 
 /* Destroy a context (the workspace remains the caller's).  NULL is a no-op. */
 nrt_status nrt_destroy(nrt_ctx* ctx);

@@ -41,7 +41,8 @@ class MergeParams(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("refill_min", C.c_int32), ("claim", C.c_int32), ("blocks_per_cu", C.c_int32)]
+    _fields_ = [("refill_min", C.c_int32), ("claim", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("graph", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -92,7 +93,7 @@ def load():
         "nrt_trace_rays_debug": (st, [_P, C.c_int64, _D, _D, C.POINTER(C.c_int32), _D, _P,
                                       C.POINTER(Budget)]),
         "nrt_healpix_dirs": (st, [_P, C.c_int32, C.c_int64, C.c_int64, _D]),
-        "nrt_last_kernel_time": (st, [_P, _D, C.POINTER(C.c_int32)]),
+        "nrt_last_kernel_time": (st, [_P, _D, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "nrt_set_tuning": (st, [_P, C.POINTER(Tuning)]),
         "nrt_get_tuning": (st, [_P, C.POINTER(Tuning)]),
         "nrt_autotune": (st, [_P, _P, C.c_int32, C.POINTER(Tuning)]),
@@ -258,12 +259,18 @@ class Context:
         last pass, from HIP events on the context's stream."""
         ms = C.c_double(0.0)
         n = C.c_int32(0)
-        _check(load().nrt_last_kernel_time(self._ctx, C.byref(ms), C.byref(n)), self._ctx)
+        _check(load().nrt_last_kernel_time(self._ctx, C.byref(ms), C.byref(n), None), self._ctx)
         return ms.value, n.value
 
-    def set_tuning(self, refill_min=0, claim=0, blocks_per_cu=0):
-        _check(load().nrt_set_tuning(self._ctx, C.byref(Tuning(refill_min, claim,
-                                                                blocks_per_cu))), self._ctx)
+    def last_pass_was_graph(self):
+        g = C.c_int32(0)
+        _check(load().nrt_last_kernel_time(self._ctx, None, None, C.byref(g)), self._ctx)
+        return bool(g.value)
+
+    def set_tuning(self, refill_min=0, claim=0, blocks_per_cu=0, graph=0):
+        """graph: 0 replay a captured pass once eligible, 1 never, 2 always try."""
+        _check(load().nrt_set_tuning(self._ctx, C.byref(Tuning(refill_min, claim, blocks_per_cu,
+                                                                graph))), self._ctx)
 
     def get_tuning(self):
         t = Tuning()

@@ -132,7 +132,7 @@ nrt_status launch_timed(nrt_ctx* c, const MarchArgs& a, int64_t rays) {
     c->ev.push_back(e);
   }
   HIP_OR_FAIL(c, hipEventRecord(c->ev[k], c->stream));
-  HIP_OR_FAIL(c, nrt::launch_march(c, a, rays));
+  HIP_OR_FAIL(c, nrt::launch_march(c, a, rays, c->stream));
   HIP_OR_FAIL(c, hipEventRecord(c->ev[k + 1], c->stream));
   c->launches += 1;
   return NRT_OK;
@@ -157,6 +157,7 @@ nrt_status process_level(nrt_ctx* c, PassState& ps, int level, bool spawn, int64
     a.in = c->queue[level];
     a.r2split = c->r2split[level];
     a.sqrt_omega = c->sqrt_omega[level];
+    a.claim_ctr = &c->acc->claim;
     unsigned long long* cnt = &c->acc->out_count[level + 1];
     if (!last) {
       a.out = c->queue[level + 1];
@@ -198,8 +199,9 @@ nrt_status finish_timing(nrt_ctx* c) {
   return NRT_OK;
 }
 
-// One trace pass over the current absorber field into gamma.
-nrt_status trace_pass(nrt_ctx* c, double* gamma, nrt_budget* out) {
+// One trace pass over the current absorber field into gamma, driven from
+// the host: level queues processed depth first in chunks.
+nrt_status chunked_pass(nrt_ctx* c, double* gamma, nrt_budget* out) {
   nrt_status st = upload_sources(c);
   if (st) return st;
   nrt_budget b;
@@ -225,6 +227,136 @@ nrt_status trace_pass(nrt_ctx* c, double* gamma, nrt_budget* out) {
   b.escaped = h.escaped;
   b.truncated = h.truncated;
   b.segments = h.segments;
+  if (out) *out = b;
+  return NRT_OK;
+}
+
+// Enqueue a device-driven pass on stream st: every level's launch reads its
+// ray count from the accumulator block (written by the previous level), so
+// the whole pass runs without a host round trip.  Needs every level to fit
+// its queue; a launch that cannot store a split sets the overflow flag.
+hipError_t enqueue_device_pass(nrt_ctx* c, hipStream_t st, double* gamma) {
+  hipError_t e = nrt::launch_zero(gamma, c->lay.cells, c->cu_count, st);
+  if (e == hipSuccess) e = nrt::launch_zero_accum(c->acc, st);
+  const int64_t m = int64_t(c->h_ndot.size());
+  const int64_t cap = c->lay.capacity;
+  for (int level = 0; level <= c->desc.l_max && e == hipSuccess; ++level) {
+    MarchArgs a = base_args(c, gamma);
+    a.level = level;
+    a.spawn = level == 0 ? 1 : 0;
+    a.begin = 0;
+    a.end = level == 0 ? 12 * m : 0;
+    a.count_src = level == 0 ? nullptr : &c->acc->out_count[level];
+    a.in_cap = cap;
+    a.in = c->queue[level];
+    a.r2split = c->r2split[level];
+    a.sqrt_omega = c->sqrt_omega[level];
+    a.claim_ctr = &c->acc->claim_lv[level];
+    if (level < c->desc.l_max) {
+      a.out = c->queue[level + 1];
+      a.out_cap = cap;
+    } else {
+      a.out = c->queue[level];
+      a.out_cap = 0;
+    }
+    e = nrt::launch_march(c, a, level == 0 ? 12 * m : cap, st);
+  }
+  return e;
+}
+
+nrt_status capture_graph(nrt_ctx* c, double* gamma) {
+  if (c->graph_exec) {
+    HIP_OR_FAIL(c, hipGraphExecDestroy(c->graph_exec));
+    c->graph_exec = nullptr;
+  }
+  if (!c->capture_stream)
+    HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+  HIP_OR_FAIL(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+  const hipError_t e = enqueue_device_pass(c, c->capture_stream, gamma);
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(c->capture_stream, &g);
+  if (e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_fail(c, e, "capture of the device-driven pass");
+  }
+  if (e2 != hipSuccess) return hip_fail(c, e2, "hipStreamEndCapture");
+  const hipError_t e3 = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e3 != hipSuccess) {
+    c->graph_exec = nullptr;
+    return hip_fail(c, e3, "hipGraphInstantiate");
+  }
+  c->graph_gamma = gamma;
+  c->graph_sources = int64_t(c->h_ndot.size());
+  c->graph_tuning = c->tuning;
+  return NRT_OK;
+}
+
+// Replay the captured device-driven pass (capturing it first if needed).
+// NRT_ERR_OVERFLOW if a level did not fit its queue (Gamma is then invalid).
+nrt_status graph_pass(nrt_ctx* c, double* gamma, nrt_budget* out) {
+  nrt_status st = upload_sources(c);
+  if (st) return st;
+  const int64_t m = int64_t(c->h_ndot.size());
+  if (!c->graph_exec || c->graph_gamma != gamma || c->graph_sources != m ||
+      std::memcmp(&c->graph_tuning, &c->tuning, sizeof(nrt_tuning)) != 0) {
+    st = capture_graph(c, gamma);
+    if (st) return st;
+  }
+  while (c->ev.size() < 2) {
+    hipEvent_t e;
+    HIP_OR_FAIL(c, hipEventCreate(&e));
+    c->ev.push_back(e);
+  }
+  HIP_OR_FAIL(c, hipEventRecord(c->ev[0], c->stream));
+  HIP_OR_FAIL(c, hipGraphLaunch(c->graph_exec, c->stream));
+  HIP_OR_FAIL(c, hipEventRecord(c->ev[1], c->stream));
+  st = sync_read_accum(c);
+  if (st) return st;
+  float ms = 0.0f;
+  HIP_OR_FAIL(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+  c->launches = c->desc.l_max + 1;
+  c->march_ms = ms;
+  const Accum& h = *c->h_acc;
+  if (h.overflow) return fail(c, NRT_ERR_OVERFLOW, "a level did not fit its queue");
+  nrt_budget b;
+  std::memset(&b, 0, sizeof(b));
+  for (double v : c->h_ndot) b.emitted += v;
+  b.absorbed = h.absorbed;
+  b.escaped = h.escaped;
+  b.truncated = h.truncated;
+  b.segments = h.segments;
+  for (int l = 0; l <= c->desc.l_max; ++l) {
+    const uint64_t k = l == 0 ? uint64_t(12 * m) : uint64_t(h.out_count[l]);
+    b.rays_per_level[l] = k;
+    b.rays += k;
+    if (l > 0) b.splits += k / 4;
+  }
+  if (out) *out = b;
+  return NRT_OK;
+}
+
+// One trace pass: replay the captured device-driven pass when every level
+// is known to fit its queue, else (or after an overflow) the chunked pass.
+nrt_status trace_pass(nrt_ctx* c, double* gamma, nrt_budget* out) {
+  const int mode = c->tuning.graph;
+  const bool sources = !c->h_ndot.empty();
+  if (sources && mode != 1 && (mode == 2 || c->graph_eligible)) {
+    const nrt_status st = graph_pass(c, gamma, out);
+    if (st == NRT_OK) {
+      c->last_pass_graph = 1;
+      return NRT_OK;
+    }
+    if (st != NRT_ERR_OVERFLOW) return st;
+    c->graph_eligible = false;
+  }
+  c->last_pass_graph = 0;
+  nrt_budget b;
+  const nrt_status st = chunked_pass(c, gamma, &b);
+  if (st) return st;
+  uint64_t widest = 0;
+  for (int l = 1; l <= c->desc.l_max; ++l) widest = std::max(widest, b.rays_per_level[l]);
+  c->graph_eligible = widest <= uint64_t(c->lay.capacity);
   if (out) *out = b;
   return NRT_OK;
 }
@@ -516,6 +648,7 @@ nrt_status nrt_trace_rays_debug(nrt_ctx* c, int64_t k, const double* origin, con
     a.inj_L = d_L;
     a.inj_level = d_lev;
     a.out_cap = 0;
+    a.claim_ctr = &c->acc->claim;
     HIP_OR_FAIL(c, hipMemsetAsync(&c->acc->claim, 0, sizeof(unsigned long long), c->stream));
     nrt_status st = launch_timed(c, a, k);
     if (st) return st;
@@ -623,7 +756,8 @@ nrt_status nrt_set_tuning(nrt_ctx* c, const nrt_tuning* t) {
   if (!c) return fail(nullptr, NRT_ERR_ARG, "ctx is NULL");
   if (!t) return fail(c, NRT_ERR_ARG, "tuning is NULL");
   if (t->refill_min < 0 || t->refill_min > 64 || t->claim < 0 || t->claim > 65536 ||
-      t->claim % 64 != 0 || t->blocks_per_cu < 0 || t->blocks_per_cu > 64)
+      t->claim % 64 != 0 || t->blocks_per_cu < 0 || t->blocks_per_cu > 64 || t->graph < 0 ||
+      t->graph > 2)
     return fail(c, NRT_ERR_ARG, "tuning out of range");
   c->tuning = *t;
   return NRT_OK;
@@ -645,7 +779,7 @@ nrt_status nrt_autotune(nrt_ctx* c, double* gamma_scratch, int32_t passes, nrt_t
     for (int claim : {0, 256, 1024})
       for (int bpc : {0, std::max(1, max_bpc - 1)}) {
         if (bpc != 0 && bpc == max_bpc) continue;
-        cand.push_back(nrt_tuning{refill, claim, bpc});
+        cand.push_back(nrt_tuning{refill, claim, bpc, keep.graph});
       }
   double best_ms = INFINITY;
   nrt_tuning win = keep;
@@ -671,16 +805,20 @@ nrt_status nrt_autotune(nrt_ctx* c, double* gamma_scratch, int32_t passes, nrt_t
   return NRT_OK;
 }
 
-nrt_status nrt_last_kernel_time(const nrt_ctx* c, double* march_ms, int32_t* launches) {
+nrt_status nrt_last_kernel_time(const nrt_ctx* c, double* march_ms, int32_t* launches,
+                                int32_t* graph_replayed) {
   if (!c) return fail(nullptr, NRT_ERR_ARG, "ctx is NULL");
   if (march_ms) *march_ms = c->launches ? c->march_ms / c->launches : 0.0;
   if (launches) *launches = c->launches;
+  if (graph_replayed) *graph_replayed = c->last_pass_graph;
   return NRT_OK;
 }
 
 nrt_status nrt_destroy(nrt_ctx* c) {
   if (!c) return NRT_OK;
   (void)hipStreamSynchronize(c->stream);
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   if (c->h_acc) (void)hipHostFree(c->h_acc);
   delete c;

@@ -36,6 +36,7 @@ struct Accum {
   unsigned long long claim;  // rays claimed so far in the current march launch
   unsigned long long out_count[kMaxLevel + 2];  // rays pushed into each level queue
   unsigned long long chem_delta_bits;  // max |dx_avg| as the bits of a non-negative double
+  unsigned long long claim_lv[kMaxLevel + 2];  // claim counters of a device-driven pass
 };
 
 struct MarchArgs {
@@ -58,8 +59,12 @@ struct MarchArgs {
   const double* src_pos;  // 3 per source
   const double* src_l0;   // rate per level-0 ray (ndot / 12)
   int64_t src_begin;
-  // input rays [begin, end)
+  // input rays [begin, end), or [0, *count_src) when count_src is set (the
+  // previous level's kernel wrote the count; at most in_cap)
   int64_t begin, end;
+  const unsigned long long* count_src;
+  int64_t in_cap;
+  unsigned long long* claim_ctr;  // rays claimed so far in this launch
   RayQueue in;
   // injected rays (level == -1)
   const double* inj_origin;
@@ -91,6 +96,14 @@ struct nrt_ctx {
   int cu_count;
   int march_blocks_per_cu;  // resident blocks of the march kernel per CU
   nrt_tuning tuning;        // launch parameters (0 = default)
+  // captured device-driven pass (hipGraph)
+  hipGraphExec_t graph_exec;
+  hipStream_t capture_stream;
+  double* graph_gamma;      // Gamma buffer the graph writes
+  int64_t graph_sources;    // source count the graph was captured for
+  nrt_tuning graph_tuning;  // launch parameters it was captured with
+  bool graph_eligible;      // a previous pass fit every level in one queue
+  int last_pass_graph;      // 1 if the last pass replayed the graph
   hipStream_t stream;
   char* ws;
   // typed views into the workspace
@@ -125,7 +138,7 @@ namespace nrt {
 hipError_t launch_prep(nrt_ctx* c);
 hipError_t launch_zero(double* p, int64_t count, int cus, hipStream_t s);
 hipError_t launch_zero_accum(Accum* acc, hipStream_t s);
-hipError_t launch_march(const nrt_ctx* c, const MarchArgs& a, int64_t rays);
+hipError_t launch_march(const nrt_ctx* c, const MarchArgs& a, int64_t rays, hipStream_t st);
 hipError_t march_blocks_per_cu(bool mixed, int* blocks);
 hipError_t launch_healpix(int level, int64_t first, int64_t count, double* out, hipStream_t s);
 

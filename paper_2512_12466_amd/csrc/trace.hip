@@ -140,6 +140,8 @@ struct RayState {
   double T, absf;   // mixed path: transmitted fraction, absorbed fraction
   double r2s, sqo;  // split radius^2 and sqrt(pixel solid angle) of the level
   float s_rate;     // mixed path: L / h^3 in FP32
+  double a64;       // absorber of the current cell, loaded ahead (FP64 path)
+  float a32;        // the same for the mixed path
   int i0, i1, i2, w0, w1, w2;
   int st0, st1, st2;
   int level;
@@ -210,6 +212,12 @@ __device__ int ray_init(RayState& R, const MarchArgs& A, int64_t r) {
   R.w0 = A.periodic ? wrap_cell(R.i0, n) : R.i0;
   R.w1 = A.periodic ? wrap_cell(R.i1, n) : R.i1;
   R.w2 = A.periodic ? wrap_cell(R.i2, n) : R.i2;
+  const int64_t n64 = n;
+  const int64_t c0 = int64_t(R.w0) + n64 * (int64_t(R.w1) + n64 * int64_t(R.w2));
+  if (MIXED)
+    R.a32 = A.a32[c0];
+  else
+    R.a64 = A.a64[c0];
   return kGoOn;
 }
 
@@ -217,7 +225,9 @@ __device__ int ray_init(RayState& R, const MarchArgs& A, int64_t r) {
 // Stop tests at the current cell boundary, then one cell segment: optical
 // depth, Eq. lut_eqn deposit with the overlap correction, advance.  The
 // caller books the photons of a ray that stops.  `inserted` counts new table
-// slots taken by this call's deposits.
+// slots taken by this call's deposits.  Memory latency is hidden by order:
+// the cell's absorber was loaded at the end of the previous step, and the
+// neighbour's is requested before the attenuation arithmetic that follows.
 template <bool MIXED, typename V>
 __device__ int ray_step(RayState& R, const MarchArgs& A, const WaveTable<V>& tab, LaneAcc& acc,
                         int& inserted) {
@@ -242,50 +252,17 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const WaveTable<V>& tab
   if (ds < 0.0) ds = 0.0;
   const int64_t c = int64_t(R.w0) + n64 * (int64_t(R.w1) + n64 * int64_t(R.w2));
 
-  // ---- segment physics (Eq. lut_eqn, Eq. optical_depth) ----
-  double G64 = 0.0, a64 = 0.0;
-  float G32 = 0.0f, a32 = 0.0f;
-  if (MIXED) {
-    a32 = fabsf(A.a32[c]);
-    const float dsf = float(ds);
-    const float dtau = A.kf * a32 * dsf;
-    const float em = -expm1f(-dtau);  // absorbed share of the entering photons
-    // transmitted fraction in FP64: the absorbed part for weak absorption,
-    // the surviving part for strong absorption (where em rounds towards 1)
-    double dT, Tn;
-    if (em < 0.5f) {
-      dT = R.T * double(em);
-      Tn = R.T - dT;
-    } else {
-      Tn = R.T * double(expf(-dtau));
-      dT = R.T - Tn;
-    }
-    const float Tf = float(R.T);
-    R.T = Tn;
-    R.absf += dT;
-    G32 = a32 > 0.0f ? (R.s_rate * float(dT)) / a32 : R.s_rate * Tf * (A.kf * dsf);
-  } else {
-    a64 = fabs(A.a64[c]);
-    const double dl = ds * A.h_cm;
-    const double dtau = A.sigma0 * a64 * dl;
-    const double dN = R.P * (-expm1(-dtau));
-    G64 = a64 > 0.0 ? dN / (a64 * A.h3) : R.P * A.sigma0 * dl / A.h3;
-    acc.absorbed += dN;
-    R.P -= dN;
-    R.tau += dtau;
-  }
-
-  // ---- overlap correction (Eqs. correction .. new_secondary) ----
-  double fc = 1.0;
-  bool secondary = false;
+  // ---- overlap geometry (Eqs. correction .. new_secondary): nearest face
+  // of the segment midpoint, and the neighbour across it ----
+  bool near = false;
+  double dedge = 0.0, lpix = 1.0;
+  bool neighbour = false;  // the neighbour's absorber is needed
   int64_t c2 = 0;
-  double a2_64 = 0.0;
-  float a2_32 = 0.0f;
+  double raw2_64 = 0.0;
+  float raw2_32 = 0.0f;
   if (A.corr != NRT_CORR_NONE) {
     const double rm = 0.5 * (R.s + tn);
-    const double lpix = rm * R.sqo;
-    // distance from the segment midpoint to the nearest face of the cell
-    double dedge;
+    lpix = rm * R.sqo;
     int fax = 0, fdir;
     {
       const double m0 = R.o0 + rm * R.d0;
@@ -313,72 +290,123 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const WaveTable<V>& tab
         fdir = dm < dp ? -1 : (dp < dm ? 1 : (R.d2 < 0.0 ? -1 : 1));
       }
     }
-    if (dedge < 0.5 * lpix) {
-      const double f = 0.5 + dedge / lpix;
-      if (A.corr == NRT_CORR_LINEAR) {
-        fc = f;
-      } else if (A.corr == NRT_CORR_SQUARED) {
-        fc = f * f;
-      } else {
-        bool usable = false;
-        const int j0 = R.i0 + (fax == 0 ? fdir : 0);
-        const int j1 = R.i1 + (fax == 1 ? fdir : 0);
-        const int j2 = R.i2 + (fax == 2 ? fdir : 0);
-        const bool j_out = j0 < 0 || j0 >= n || j1 < 0 || j1 >= n || j2 < 0 || j2 >= n;
-        if (!open_box || !j_out) {
-          const int v0 = fax == 0 ? (open_box ? j0 : wrap_step(R.w0, fdir, n)) : R.w0;
-          const int v1 = fax == 1 ? (open_box ? j1 : wrap_step(R.w1, fdir, n)) : R.w1;
-          const int v2 = fax == 2 ? (open_box ? j2 : wrap_step(R.w2, fdir, n)) : R.w2;
-          c2 = int64_t(v0) + n64 * (int64_t(v1) + n64 * int64_t(v2));
-          if (MIXED) {
-            const float raw = A.a32[c2];
-            usable = !__builtin_signbit(raw);
-            a2_32 = raw;
-          } else {
-            const double raw = A.a64[c2];
-            usable = !__builtin_signbit(raw);
-            a2_64 = raw;
-          }
-        }
-        if (A.corr == NRT_CORR_CONSERVATIVE) {
-          if (usable) fc = f;
-        } else {  // NAIVE
-          fc = f;
-        }
-        secondary = usable;
+    near = dedge < 0.5 * lpix;
+    if (near && (A.corr == NRT_CORR_CONSERVATIVE || A.corr == NRT_CORR_NAIVE)) {
+      const int j0 = R.i0 + (fax == 0 ? fdir : 0);
+      const int j1 = R.i1 + (fax == 1 ? fdir : 0);
+      const int j2 = R.i2 + (fax == 2 ? fdir : 0);
+      const bool j_out = j0 < 0 || j0 >= n || j1 < 0 || j1 >= n || j2 < 0 || j2 >= n;
+      if (!open_box || !j_out) {
+        const int v0 = fax == 0 ? (open_box ? j0 : wrap_step(R.w0, fdir, n)) : R.w0;
+        const int v1 = fax == 1 ? (open_box ? j1 : wrap_step(R.w1, fdir, n)) : R.w1;
+        const int v2 = fax == 2 ? (open_box ? j2 : wrap_step(R.w2, fdir, n)) : R.w2;
+        c2 = int64_t(v0) + n64 * (int64_t(v1) + n64 * int64_t(v2));
+        neighbour = true;
+        if (MIXED)
+          raw2_32 = A.a32[c2];
+        else
+          raw2_64 = A.a64[c2];
       }
+    }
+  }
+
+  // ---- segment physics (Eq. lut_eqn, Eq. optical_depth) ----
+  double G64 = 0.0, a64 = 0.0;
+  float G32 = 0.0f, a32 = 0.0f;
+  if (MIXED) {
+    a32 = fabsf(R.a32);
+    const float dsf = float(ds);
+    const float dtau = A.kf * a32 * dsf;
+    const float em = -expm1f(-dtau);  // absorbed share of the entering photons
+    // transmitted fraction in FP64: the absorbed part for weak absorption,
+    // the surviving part for strong absorption (where em rounds towards 1)
+    double dT, Tn;
+    if (em < 0.5f) {
+      dT = R.T * double(em);
+      Tn = R.T - dT;
+    } else {
+      Tn = R.T * double(expf(-dtau));
+      dT = R.T - Tn;
+    }
+    const float Tf = float(R.T);
+    R.T = Tn;
+    R.absf += dT;
+    G32 = a32 > 0.0f ? (R.s_rate * float(dT)) / a32 : R.s_rate * Tf * (A.kf * dsf);
+  } else {
+    a64 = fabs(R.a64);
+    const double dl = ds * A.h_cm;
+    const double dtau = A.sigma0 * a64 * dl;
+    const double dN = R.P * (-expm1(-dtau));
+    G64 = a64 > 0.0 ? dN / (a64 * A.h3) : R.P * A.sigma0 * dl / A.h3;
+    acc.absorbed += dN;
+    R.P -= dN;
+    R.tau += dtau;
+  }
+
+  // ---- overlap correction values (the decision above is FP64; the factor
+  // is FP32 in the mixed path) ----
+  using R_t = typename std::conditional<MIXED, float, double>::type;
+  R_t fc = R_t(1);
+  bool secondary = false;
+  if (near) {
+    const bool usable = neighbour && !(MIXED ? __builtin_signbit(raw2_32) : __builtin_signbit(raw2_64));
+    const R_t f = R_t(0.5) + R_t(dedge) / R_t(lpix);
+    if (A.corr == NRT_CORR_LINEAR) {
+      fc = f;
+    } else if (A.corr == NRT_CORR_SQUARED) {
+      fc = f * f;
+    } else if (A.corr == NRT_CORR_CONSERVATIVE) {
+      if (usable) fc = f;
+      secondary = usable;
+    } else {  // NAIVE
+      fc = f;
+      secondary = usable;
     }
   }
 
   // ---- deposit ----
   if constexpr (MIXED) {
-    const float fcf = float(fc);
-    inserted += tab.add(c, fcf * G32) ? 1 : 0;
-    if (secondary) inserted += tab.add(c2, ((1.0f - fcf) * (a32 / a2_32)) * G32) ? 1 : 0;
+    inserted += tab.add(c, fc * G32) ? 1 : 0;
+    if (secondary) inserted += tab.add(c2, ((1.0f - fc) * (a32 / raw2_32)) * G32) ? 1 : 0;
   } else {
     inserted += tab.add(c, fc * G64) ? 1 : 0;
-    if (secondary) inserted += tab.add(c2, ((1.0 - fc) * (a64 / a2_64)) * G64) ? 1 : 0;
+    if (secondary) inserted += tab.add(c2, ((1.0 - fc) * (a64 / raw2_64)) * G64) ? 1 : 0;
   }
 
-  // ---- advance one cell ----
+  // ---- advance one cell: step the winning axis (its component is nonzero)
+  // and recompute its next plane crossing, without diverging on the axis ----
   R.s = tn;
-  if (ax == 0) {
-    R.i0 += R.st0;
-    R.w0 = open_box ? R.i0 : wrap_step(R.w0, R.st0, n);
-    R.t0 = plane_t(R.o0, R.d0, R.i0);
-  } else if (ax == 1) {
-    R.i1 += R.st1;
-    R.w1 = open_box ? R.i1 : wrap_step(R.w1, R.st1, n);
-    R.t1 = plane_t(R.o1, R.d1, R.i1);
-  } else {
-    R.i2 += R.st2;
-    R.w2 = open_box ? R.i2 : wrap_step(R.w2, R.st2, n);
-    R.t2 = plane_t(R.o2, R.d2, R.i2);
+  {
+    // exact masked sums (o and d are finite), which keep the ray state in
+    // registers where a chain of selects over its fields would not
+    const double m0 = ax == 0 ? 1.0 : 0.0, m1 = ax == 1 ? 1.0 : 0.0, m2 = ax == 2 ? 1.0 : 0.0;
+    const int k0 = ax == 0, k1 = ax == 1, k2 = ax == 2;
+    const double o_a = R.o0 * m0 + R.o1 * m1 + R.o2 * m2;
+    const double d_a = R.d0 * m0 + R.d1 * m1 + R.d2 * m2;
+    const int st_a = R.st0 * k0 + R.st1 * k1 + R.st2 * k2;
+    const int i_a = R.i0 * k0 + R.i1 * k1 + R.i2 * k2 + st_a;
+    const int w_a = open_box ? i_a : wrap_step(R.w0 * k0 + R.w1 * k1 + R.w2 * k2, st_a, n);
+    const double t_a = (double(st_a > 0 ? i_a + 1 : i_a) - o_a) / d_a;
+    R.i0 = ax == 0 ? i_a : R.i0;
+    R.i1 = ax == 1 ? i_a : R.i1;
+    R.i2 = ax == 2 ? i_a : R.i2;
+    R.w0 = ax == 0 ? w_a : R.w0;
+    R.w1 = ax == 1 ? w_a : R.w1;
+    R.w2 = ax == 2 ? w_a : R.w2;
+    R.t0 = ax == 0 ? t_a : R.t0;
+    R.t1 = ax == 1 ? t_a : R.t1;
+    R.t2 = ax == 2 ? t_a : R.t2;
   }
   acc.segments += 1;
   if (open_box &&
       (R.i0 < 0 || R.i0 >= n || R.i1 < 0 || R.i1 >= n || R.i2 < 0 || R.i2 >= n))
     return kEscaped;
+  // absorber of the next cell, consumed by the next step
+  const int64_t cn = int64_t(R.w0) + n64 * (int64_t(R.w1) + n64 * int64_t(R.w2));
+  if (MIXED)
+    R.a32 = A.a32[cn];
+  else
+    R.a64 = A.a64[cn];
   return kGoOn;
 }
 
@@ -441,7 +469,11 @@ __global__ __launch_bounds__(kBlock) void k_march(MarchArgs A) {
   bool pend = false;
   uint32_t p_src = 0, p_pix = 0;
   double p_s = 0.0, p_w = 0.0;
-  const int64_t total = A.end - A.begin;
+  int64_t total = A.end - A.begin;
+  if (A.count_src) {
+    const int64_t k = int64_t(*A.count_src);
+    total = k < A.in_cap ? k : A.in_cap;
+  }
   const int64_t claim = A.claim;
   int64_t pool = 0, pool_end = 0;  // wavefront-uniform run of claimed rays
   bool exhausted = total <= 0;
@@ -452,7 +484,7 @@ __global__ __launch_bounds__(kBlock) void k_march(MarchArgs A) {
     if (!exhausted && (n_idle >= A.refill_min || n_idle == 64)) {
       if (pool == pool_end) {
         unsigned long long b = 0;
-        if (lane == 0) b = atomicAdd(&A.acc->claim, static_cast<unsigned long long>(claim));
+        if (lane == 0) b = atomicAdd(A.claim_ctr, static_cast<unsigned long long>(claim));
         b = read_lane64(b, 0);
         if (int64_t(b) >= total) {
           exhausted = true;
@@ -618,7 +650,7 @@ hipError_t march_blocks_per_cu(bool mixed, int* blocks) {
 }
 
 // persistent grid: as many blocks as stay resident, or fewer for small launches
-hipError_t launch_march(const nrt_ctx* c, const MarchArgs& args, int64_t rays) {
+hipError_t launch_march(const nrt_ctx* c, const MarchArgs& args, int64_t rays, hipStream_t st) {
   int per_cu = c->march_blocks_per_cu > 0 ? c->march_blocks_per_cu : 2;
   if (c->tuning.blocks_per_cu > 0 && c->tuning.blocks_per_cu < per_cu)
     per_cu = c->tuning.blocks_per_cu;
@@ -630,9 +662,9 @@ hipError_t launch_march(const nrt_ctx* c, const MarchArgs& args, int64_t rays) {
   a.claim = c->tuning.claim > 0 ? c->tuning.claim : 64;
   a.refill_min = c->tuning.refill_min > 0 ? c->tuning.refill_min : 16;
   if (c->desc.precision == NRT_MIXED)
-    hipLaunchKernelGGL(k_march<true>, dim3(blocks), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(k_march<true>, dim3(blocks), dim3(kBlock), 0, st, a);
   else
-    hipLaunchKernelGGL(k_march<false>, dim3(blocks), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(k_march<false>, dim3(blocks), dim3(kBlock), 0, st, a);
   return hipGetLastError();
 }
 

@@ -277,3 +277,59 @@ def test_bubbles_256_4096_sources(gpu, orc):
     gm, bm = run_gpu(gpu, w.n, w.h_cm, w.n_H, w.x, s.pos, s.ndot, 1, **kw)
     assert rel_err(gm, ref)[0] <= 1e-4
     assert budget_err(bm, rb) <= 1e-6
+
+
+def test_graph_replays_match_eager_passes(gpu, orc):
+    """Once a pass shows every level fits its queue, later passes replay a
+    captured device-driven pass (hipGraph).  Every replay, with eager work
+    and synchronisation between them, must equal the eager chunked pass and
+    the oracle; changing the sources or the output buffer re-captures; a
+    queue too small for a level falls back to the chunked pass."""
+    import torch
+    n = 32
+    nH, x, pos, ndot, h = field_case(n, 51, ionized=0.4, m=6, tau_cell=0.3)
+    kw = dict(periodic=True, n_min_ray=4.0, l_max=7, tau_max=30.0, n_th=4e-4)
+    ref, rb = orc.trace(orc.make_params(n, h, **kw), nH, x, pos, ndot)
+    # The mixed path sums its deposits in FP32 LDS slots whose order of
+    # arrival varies from pass to pass, so replays agree to FP32 rounding of
+    # those partial sums (all terms positive: relative error <= k * 2^-24 for
+    # k deposits per slot between flushes); the FP64 path to 1e-12.
+    for prec, tol, rep_tol in ((0, 1e-10, 1e-12), (1, 1e-4, 2e-5)):
+        ctx = gpu.init_grid(gpu.make_desc(n, h, precision=prec, **kw), nH, x, device="cuda:0",
+                            max_sources=16, ray_capacity=1 << 21)
+        ctx.add_sources(pos, ndot)
+        g_eager, b_eager = ctx.trace_step()
+        assert not ctx.last_pass_was_graph()
+        eager = g_eager.cpu().numpy()
+        assert rel_err(eager, ref)[0] <= tol
+        for rep in range(4):
+            junk = torch.randn(1 << 20, device="cuda:0").sum()  # eager work in between
+            torch.cuda.synchronize()
+            g, b = ctx.trace_step(g_eager)
+            assert ctx.last_pass_was_graph(), rep
+            got = g.cpu().numpy()
+            np.testing.assert_allclose(got, eager, rtol=rep_tol, atol=1e-14 * eager.max())
+            for k in ("segments", "rays", "splits", "rays_per_level"):
+                assert b[k] == b_eager[k], (rep, k)
+            assert abs(b["absorbed"] - b_eager["absorbed"]) <= 1e-12 * b["emitted"]
+            del junk
+        # a new output buffer and a changed source list are captured again
+        g2, b2 = ctx.trace_step()
+        assert ctx.last_pass_was_graph()
+        np.testing.assert_allclose(g2.cpu().numpy(), eager, rtol=rep_tol,
+                                   atol=1e-14 * eager.max())
+        ctx.add_sources(pos[:2], ndot[:2])
+        ref2, rb2 = orc.trace(orc.make_params(n, h, **kw), nH, x, np.vstack([pos, pos[:2]]),
+                              np.concatenate([ndot, ndot[:2]]))
+        g3, b3 = ctx.trace_step()
+        assert rel_err(g3.cpu().numpy(), ref2)[0] <= tol
+        ctx.destroy()
+    # forced graph with a queue too small: overflow, then the chunked pass
+    ctx = gpu.init_grid(gpu.make_desc(n, h, **kw), nH, x, device="cuda:0", max_sources=16,
+                        ray_capacity=4096)
+    ctx.add_sources(pos, ndot)
+    ctx.set_tuning(graph=2)
+    g, b = ctx.trace_step()
+    assert not ctx.last_pass_was_graph()
+    assert rel_err(g.cpu().numpy(), ref)[0] <= 1e-10 and b["segments"] == rb["segments"]
+    ctx.destroy()

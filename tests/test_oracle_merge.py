@@ -133,3 +133,23 @@ def test_merge_centroid_snap_exact(orc):
     # without periodic wrap the two are far apart and stay separate
     mc, _, _ = orc.merge_sources(mp, n, False, x, pos, [1.0, 3.0])
     assert len(mc) == 2
+
+
+def test_max_radius_few_samples_need_all_ionized(orc):
+    """When a shell holds fewer than N_min distinct sample cells, every one
+    must be ionized (Alg. source_merge).  With the 12 level-0 directions the
+    first shell has at most 12 samples: a single neutral sample cell then
+    stops the growth at 0 under N_min = 20, but not under N_min = 1 with
+    f_req = 0.9 when 11 of 12 samples are ionized."""
+    n = 24
+    c = np.array([[12, 12, 12]])
+    x = np.ones((n, n, n))
+    d = orc.pix2vec_nest(0, 4)  # the +x equatorial direction
+    p = np.floor(c[0] + 0.5 + 2.0 * d).astype(int)
+    x[p[2], p[1], p[0]] = 0.0  # that sample cell is neutral
+    mp = orc.make_merge_params(dr=2.0, r_max=6.0, n_min=20, shell_level=0, f_req=0.9)
+    assert orc.max_radius(mp, n, True, x, c)[0] == 0.0
+    mp = orc.make_merge_params(dr=2.0, r_max=2.0, n_min=1, shell_level=0, f_req=0.9)
+    assert orc.max_radius(mp, n, True, x, c)[0] == 2.0  # 11/12 >= 0.9
+    mp = orc.make_merge_params(dr=2.0, r_max=2.0, n_min=1, shell_level=0, f_req=0.95)
+    assert orc.max_radius(mp, n, True, x, c)[0] == 0.0  # 11/12 < 0.95

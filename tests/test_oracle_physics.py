@@ -204,3 +204,32 @@ def test_inverse_square_thin_medium(orc):
         assert gamma[sel].mean() / exact[sel].mean() == pytest.approx(1.0, abs=0.02), r0
     a = (1 - x) * nH
     assert (gamma * a * h ** 3).sum() == pytest.approx(b["absorbed"], rel=1e-12)
+
+
+def test_correction_variant_identities(orc):
+    """Exact consequences of the definitions, on a field where every cell
+    keeps some neutral gas (a > 0): naive thresholding with n_th = 0 is the
+    conservative scheme (every neighbour is usable, so both apply f_c and
+    deposit the neighbour share); with a threshold above every density no
+    neighbour is usable, so naive thresholding is Eq. correction alone
+    (LINEAR) and the conservative scheme deposits everything in the cell
+    (NONE); squaring f_c <= 1 loses more photons than LINEAR."""
+    n, h, nH, x, pos, ndot, _ = _field_case(seed=33)
+    x = np.minimum(x, 1.0 - 1e-4)
+    kw = dict(periodic=True, n_min_ray=4.0, l_max=6, tau_max=20.0)
+    run = lambda corr, n_th: orc.trace(orc.make_params(n, h, corr=corr, n_th=n_th, **kw),
+                                       nH, x, pos, ndot, nthreads=1)  # one summation order
+    g_naive0, _ = run(orc.CORR_NAIVE, 0.0)
+    g_cons0, _ = run(orc.CORR_CONSERVATIVE, 0.0)
+    np.testing.assert_array_equal(g_naive0, g_cons0)
+    big = 10.0 * nH.max()
+    g_naive_big, _ = run(orc.CORR_NAIVE, big)
+    g_lin, b_lin = run(orc.CORR_LINEAR, big)
+    np.testing.assert_array_equal(g_naive_big, g_lin)
+    g_cons_big, b = run(orc.CORR_CONSERVATIVE, big)
+    g_none, _ = run(orc.CORR_NONE, big)
+    np.testing.assert_array_equal(g_cons_big, g_none)  # nothing usable: f_c = 1 everywhere
+    g_sq, _ = run(orc.CORR_SQUARED, big)
+    a = (1 - x) * nH
+    dep = lambda g: (g * a * h ** 3).sum()
+    assert dep(g_sq) < dep(g_lin) < b_lin["absorbed"]
