@@ -68,7 +68,8 @@ def run_path(nrt, w, precision, steps, warmup, capacity, graph=0):
     wall = time.perf_counter() - t0
     graph = ctx.last_pass_was_graph()
     ctx.destroy()
-    return dict(wall_s=wall, ms_per_step=1e3 * wall / steps, segments_per_step=segs // steps,
+    return dict(wall_s=wall, steps=steps, ms_per_step=1e3 * wall / steps,
+                segments_per_step=segs // steps,
                 segments_per_s=segs / wall, kernel_ms_total=kernel_ms, launches=launches,
                 avg_launch_ms=kernel_ms / max(launches, 1), budget=b, graph=graph)
 
@@ -82,18 +83,22 @@ def roofline(path, res, counters=None):
     achieved = BYTES_PER_SEGMENT[path] * res["segments_per_s_kernel"] / 1e9
     traffic = None
     mode = "graph" if res.get("graph") else "host"
-    if counters and counters.get("mode") == mode and f"{path}_traffic_bytes_per_launch" in counters:
+    if counters and counters.get(f"{path}_mode") == mode and \
+            f"{path}_traffic_bytes_per_launch" in counters:
         traffic = float(counters[f"{path}_traffic_bytes_per_launch"])
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "k_march", "bytes_per_segment": BYTES_PER_SEGMENT[path],
-            "avg_launch_ms": round(res["avg_launch_ms"], 4), "launches": res["launches"]}
+            "avg_launch_ms": round(res["avg_launch_ms"], 4), "launches": res["launches"],
+            "algorithmic_bytes_per_launch": round(
+                BYTES_PER_SEGMENT[path] * res["segments_per_step"] * res["steps"]
+                / max(res["launches"], 1), 1),
+            "mode": mode}
 
 
 KERNEL_SOURCES = ["paper_2512_12466_amd/csrc/trace.hip", "paper_2512_12466_amd/csrc/healpix.h",
                   "paper_2512_12466_amd/csrc/internal.h"]
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_march_counters_lognormal-128-64src.txt")
-LEVELS_PER_PASS = 10  # march launches of one replayed pass of lognormal-128-64src (l_max 9)
 
 
 def kernel_hash():
@@ -122,13 +127,24 @@ def read_counters():
 def summarize_counters(d, out):
     """Summarize two rocprofv3 --pmc runs of `bench.py --calibrate-copy 1024`
     (FETCH_SIZE in fetch_counter_collection.csv, WRITE_SIZE in
-    write_counter_collection.csv): each counter is scaled by what it reads
-    for the calibration copies of known size, then averaged per launch."""
+    write_counter_collection.csv, each run's JSON line in fetch_bench.json /
+    write_bench.json): each counter is scaled by what it reads for the
+    calibration copies of known size, then averaged over the march launches
+    of the run's last (timed) step, whose count and mode (host-driven or
+    graph replay) the JSON line gives."""
     import csv
     import collections
 
-    def load(name):
-        # per path, keep the dispatches of the last pass (the timed replay)
+    def bench_line(name):
+        line = [x for x in open(os.path.join(d, name)) if x.startswith("{")][-1]
+        j = json.loads(line)
+        per = {j["config"]["path"]: j["roofline"]}
+        for k, v in j.items():
+            if k.endswith("_path"):
+                per[k[:-5]] = v["roofline"]
+        return {p: (r["launches"] // j["steps"], r["mode"]) for p, r in per.items()}
+
+    def load(name, last):
         rows = collections.defaultdict(dict)
         for r in csv.DictReader(open(os.path.join(d, name))):
             k = r["Kernel_Name"]
@@ -141,30 +157,37 @@ def summarize_counters(d, out):
         for key, per in rows.items():
             ids = sorted(per)
             if key != "copy":
-                ids = ids[-(LEVELS_PER_PASS):]
-            agg[key] = [sum(per[i] for i in ids), set(ids)]
+                ids = ids[-last[key][0]:]
+            agg[key] = (sum(per[i] for i in ids), len(ids))
         return agg
-    fetch, write = load("fetch_counter_collection.csv"), load("write_counter_collection.csv")
+    lf, lw = bench_line("fetch_bench.json"), bench_line("write_bench.json")
+    # the chunking of a host-driven pass follows the order in which children
+    # reach the queue, so the launch count may differ by one between runs
+    assert {p: m for p, (_, m) in lf.items()} == {p: m for p, (_, m) in lw.items()}, (lf, lw)
+    fetch, write = load("fetch_counter_collection.csv", lf), load("write_counter_collection.csv", lw)
     copy_bytes = 3 * 1024 * 2 ** 20  # three 1024 MiB copies read and write this much
     ff = fetch["copy"][0] / copy_bytes
     fw = write["copy"][0] / copy_bytes
-    lines = [f"# HBM traffic of k_march from FETCH_SIZE / WRITE_SIZE counter runs",
-             f"# command: rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv "
-             f"-d <dir> -o fetch|write -- python3 bench.py --steps 1 --warmup 1 "
-             f"--no-cpu-baseline --calibrate-copy 1024",
-             f"# summarized with: python bench.py --summarize-counters <dir>",
-             f"# the timed step replays the captured pass (the warm-up pass is host-driven)",
+    lines = ["# HBM traffic of k_march from FETCH_SIZE / WRITE_SIZE counter runs",
+             "# command (FETCH_SIZE; then WRITE_SIZE with -o write > write_bench.json): "
+             "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o fetch -- "
+             "python3 bench.py --steps 1 --warmup 1 --no-cpu-baseline --calibrate-copy 1024 "
+             "> <dir>/fetch_bench.json",
+             "# summarized with: python bench.py --summarize-counters <dir>",
+             "# bytes per launch: counter KiB x 1024 / copy factor, averaged over the march "
+             "launches of the timed step",
              f"kernel_sha = {kernel_hash()}",
-             f"mode = graph",
              f"copy_factor_fetch = {ff:.4f}", f"copy_factor_write = {fw:.4f}"]
     for path in ("mixed", "fp64"):
-        nf, nw = len(fetch[path][1]), len(write[path][1])
-        fb = fetch[path][0] / ff / max(nf, 1)
-        wb = write[path][0] / fw / max(nw, 1)
-        lines += [f"{path}_fetch_bytes_per_launch = {fb:.1f}",
+        if path not in lf:
+            continue
+        fb = fetch[path][0] / ff / fetch[path][1]
+        wb = write[path][0] / fw / write[path][1]
+        lines += [f"{path}_mode = {lf[path][1]}",
+                  f"{path}_launches = {lf[path][0]} (fetch run), {lw[path][0]} (write run)",
+                  f"{path}_fetch_bytes_per_launch = {fb:.1f}",
                   f"{path}_write_bytes_per_launch = {wb:.1f}",
-                  f"{path}_traffic_bytes_per_launch = {fb + wb:.1f}",
-                  f"{path}_launches = {nf}"]
+                  f"{path}_traffic_bytes_per_launch = {fb + wb:.1f}"]
     open(out, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
