@@ -70,7 +70,7 @@ struct LaneAcc {
 };
 
 // Per-wavefront Gamma accumulator in LDS.  A wavefront marches rays claimed
-// in runs of kClaim consecutive queue entries; nested HEALPix order is a
+// in runs of consecutive queue entries; nested HEALPix order is a
 // Z-order curve and children are queued next to each other, so such a run
 // is a bundle of neighbouring pixels of one source and level, and by the
 // split rule it crosses each cell several times.  Deposits are summed in an
@@ -81,7 +81,6 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kWaveSlots = 1024;
 constexpr int kFlushAt = kWaveSlots / 2;
 constexpr int kProbe = 16;
-constexpr int kClaim = 256;
 constexpr uint32_t kEmpty = 0xffffffffu;
 
 template <typename V>
@@ -317,7 +316,15 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const WaveTable<V>& tab
     a32 = fabsf(R.a32);
     const float dsf = float(ds);
     const float dtau = A.kf * a32 * dsf;
-    const float em = -expm1f(-dtau);  // absorbed share of the entering photons
+    // surviving share e = exp(-dtau) from the hardware base-2 exponential
+    // (1 ulp); absorbed share em = 1 - e, which for dtau < 1/8 comes from
+    // its series (relative truncation error below dtau^5/720 < 5e-8) since
+    // 1 - e would cancel there
+    const float e = __builtin_amdgcn_exp2f(dtau * -1.44269504f);
+    const float poly =
+        dtau * fmaf(dtau, fmaf(dtau, fmaf(dtau, fmaf(dtau, 1.0f / 120.0f, -1.0f / 24.0f),
+                                          1.0f / 6.0f), -0.5f), 1.0f);
+    const float em = dtau < 0.125f ? poly : 1.0f - e;
     // transmitted fraction in FP64: the absorbed part for weak absorption,
     // the surviving part for strong absorption (where em rounds towards 1)
     double dT, Tn;
@@ -325,13 +332,14 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const WaveTable<V>& tab
       dT = R.T * double(em);
       Tn = R.T - dT;
     } else {
-      Tn = R.T * double(expf(-dtau));
+      Tn = R.T * double(e);
       dT = R.T - Tn;
     }
     const float Tf = float(R.T);
     R.T = Tn;
     R.absf += dT;
-    G32 = a32 > 0.0f ? (R.s_rate * float(dT)) / a32 : R.s_rate * Tf * (A.kf * dsf);
+    G32 = a32 > 0.0f ? (R.s_rate * float(dT)) * __builtin_amdgcn_rcpf(a32)
+                     : R.s_rate * Tf * (A.kf * dsf);
   } else {
     a64 = fabs(R.a64);
     const double dl = ds * A.h_cm;
@@ -350,7 +358,11 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const WaveTable<V>& tab
   bool secondary = false;
   if (near) {
     const bool usable = neighbour && !(MIXED ? __builtin_signbit(raw2_32) : __builtin_signbit(raw2_64));
-    const R_t f = R_t(0.5) + R_t(dedge) / R_t(lpix);
+    R_t f;
+    if constexpr (MIXED)
+      f = 0.5f + float(dedge) * __builtin_amdgcn_rcpf(float(lpix));
+    else
+      f = 0.5 + dedge / lpix;
     if (A.corr == NRT_CORR_LINEAR) {
       fc = f;
     } else if (A.corr == NRT_CORR_SQUARED) {
@@ -367,7 +379,8 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const WaveTable<V>& tab
   // ---- deposit ----
   if constexpr (MIXED) {
     inserted += tab.add(c, fc * G32) ? 1 : 0;
-    if (secondary) inserted += tab.add(c2, ((1.0f - fc) * (a32 / raw2_32)) * G32) ? 1 : 0;
+    if (secondary)
+      inserted += tab.add(c2, ((1.0f - fc) * (a32 * __builtin_amdgcn_rcpf(raw2_32))) * G32) ? 1 : 0;
   } else {
     inserted += tab.add(c, fc * G64) ? 1 : 0;
     if (secondary) inserted += tab.add(c2, ((1.0 - fc) * (a64 / raw2_64)) * G64) ? 1 : 0;
