@@ -115,7 +115,7 @@ MarchArgs base_args(const nrt_ctx* c, double* gamma) {
   a.src_l0 = c->src_l0;
   for (int l = 0; l <= nrt::kMaxLevel; ++l) a.sqrt_omega_tab[l] = c->sqrt_omega[l];
   a.acc = c->acc;
-  a.lds_keys_fit = (int64_t(d.n) * d.n * d.n < (int64_t(1) << 32) - 1) ? 1 : 0;
+  a.lds_keys_fit = ((int64_t(d.n) * d.n * d.n) >> 3 < (int64_t(1) << 32) - 1) ? 1 : 0;
   return a;
 }
 

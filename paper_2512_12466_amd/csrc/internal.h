@@ -44,7 +44,7 @@ struct MarchArgs {
   int32_t n, periodic, corr, l_max;
   int32_t level;     // HEALPix level of every input ray (-1: injected rays)
   int32_t spawn;     // 1: input ray r is (src_begin + r/12, pix r%12, s 0, w 0/1)
-  int32_t lds_keys_fit;  // 1: flat cell indices fit 32 bits (Gamma staged in LDS)
+  int32_t lds_keys_fit;  // 1: line indices (cell >> 3) fit 32 bits (Gamma staged in LDS)
   int32_t refill_min;    // idle lanes that trigger a refill of a wavefront
   int64_t claim;         // rays a wavefront claims at a time
   double h_cm, sigma0, tau_max, s_max, h3;

@@ -70,39 +70,48 @@ struct LaneAcc {
 };
 
 // Per-wavefront Gamma accumulator in LDS.  A wavefront marches rays claimed
-// in runs of consecutive queue entries; nested HEALPix order is a
-// Z-order curve and children are queued next to each other, so such a run
-// is a bundle of neighbouring pixels of one source and level, and by the
-// split rule it crosses each cell several times.  Deposits are summed in an
-// open-addressing hash table keyed by the cell index and folded into Gamma
-// with one global atomic per distinct cell when the table is half full.  A
-// deposit that finds no slot within kProbe probes goes straight to Gamma.
+// in runs of consecutive queue entries; nested HEALPix order is a Z-order
+// curve and children are queued next to each other, so such a run is a
+// bundle of neighbouring pixels of one source and level, and by the split
+// rule it crosses each cell several times.  Deposits are summed in an
+// open-addressing hash table whose slots are 64-byte lines of Gamma (kLine
+// consecutive cells along x), and folded into Gamma when half the slots are
+// taken: the device performs FP64 atomics per 64-byte line request, so the
+// flush, in which lanes 8j..8j+7 of an instruction cover the cells of one
+// line, costs one request per line instead of one per cell.  A deposit that
+// finds no slot within kProbe probes goes straight to Gamma.
 constexpr int kWaves = kBlock / 64;
-constexpr int kWaveSlots = 1024;
-constexpr int kFlushAt = kWaveSlots / 2;
+constexpr int kLine = 8;
 constexpr int kProbe = 16;
 constexpr uint32_t kEmpty = 0xffffffffu;
 
 template <typename V>
-struct WaveTable {
-  uint32_t* key;
-  V* val;
+struct LineTable {
+  // line slots per wavefront: 36 KiB (FP32 sums) or 34 KiB (FP64) per block
+  static constexpr int kLog2Lines = sizeof(V) == 4 ? 8 : 7;
+  static constexpr int kLines = 1 << kLog2Lines;
+  static constexpr int kFlushAt = kLines / 2;
+  static constexpr size_t kWaveBytes = kLines * (sizeof(uint32_t) + kLine * sizeof(V));
+
+  uint32_t* key;  // [kLines] line index (cell >> 3) or kEmpty
+  V* val;         // [kLines * kLine] partial sums of the line's cells
   double* gamma;
-  bool on;  // false when flat cell indices do not fit 32 bits
+  bool on;  // false when line indices do not fit 32 bits below kEmpty
 
   // returns true if the deposit occupied a new slot
   __device__ __forceinline__ bool add(int64_t c, V v) const {
     if (on) {
-      const uint32_t k = uint32_t(c);
-      uint32_t h = (k * 2654435761u) >> 22;
+      const uint32_t k = uint32_t(c >> 3);
+      const uint32_t sub = uint32_t(c) & uint32_t(kLine - 1);
+      uint32_t h = (k * 2654435761u) >> (32 - kLog2Lines);
 #pragma unroll 1
       for (int probe = 0; probe < kProbe; ++probe) {
         const uint32_t old = atomicCAS(&key[h], kEmpty, k);
         if (old == kEmpty || old == k) {
-          atomicAdd(&val[h], v);
+          atomicAdd(&val[h * kLine + sub], v);
           return old == kEmpty;
         }
-        h = (h + 1) & (kWaveSlots - 1);
+        h = (h + 1) & uint32_t(kLines - 1);
       }
     }
     atomicAdd(gamma + c, double(v));
@@ -110,17 +119,24 @@ struct WaveTable {
   }
 
   // whole wavefront: fold the table into Gamma and clear it (LDS operations
-  // of one wavefront complete in program order)
+  // of one wavefront complete in program order).  Cells of a line that got
+  // no deposit hold zero and are skipped, so no address past the grid is
+  // formed.
   __device__ __forceinline__ void flush(int lane) const {
     __builtin_amdgcn_wave_barrier();
-    for (int q = lane; q < kWaveSlots; q += 64) {
+    const int sub = lane & (kLine - 1);
+    for (int q = lane / kLine; q < kLines; q += 64 / kLine) {
       const uint32_t k = key[q];
       if (k != kEmpty) {
-        atomicAdd(gamma + k, double(val[q]));
-        key[q] = kEmpty;
-        val[q] = V(0);
+        const V v = val[q * kLine + sub];
+        if (v != V(0)) {
+          atomicAdd(gamma + ((int64_t(k) << 3) + sub), double(v));
+          val[q * kLine + sub] = V(0);
+        }
       }
     }
+    __builtin_amdgcn_wave_barrier();
+    for (int q = lane; q < kLines; q += 64) key[q] = kEmpty;
     __builtin_amdgcn_wave_barrier();
   }
 };
@@ -228,7 +244,7 @@ __device__ int ray_init(RayState& R, const MarchArgs& A, int64_t r) {
 // the cell's absorber was loaded at the end of the previous step, and the
 // neighbour's is requested before the attenuation arithmetic that follows.
 template <bool MIXED, typename V>
-__device__ int ray_step(RayState& R, const MarchArgs& A, const WaveTable<V>& tab, LaneAcc& acc,
+__device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab, LaneAcc& acc,
                         int& inserted) {
   const int n = A.n;
   const int64_t n64 = n;
@@ -463,16 +479,16 @@ template <bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_march(MarchArgs A) {
   using V = typename std::conditional<MIXED, float, double>::type;
   // per-wavefront deposit tables, reused for the budget reduction at the end
-  __shared__ __align__(16) unsigned char lds[kWaves * kWaveSlots * (sizeof(uint32_t) + sizeof(V))];
+  using Tab = LineTable<V>;
+  __shared__ __align__(16) unsigned char lds[kWaves * Tab::kWaveBytes];
   const int wave = threadIdx.x >> 6;
   const int lane = __lane_id();
-  uint32_t* key = reinterpret_cast<uint32_t*>(lds) + wave * kWaveSlots;
-  V* val = reinterpret_cast<V*>(lds + kWaves * kWaveSlots * sizeof(uint32_t)) + wave * kWaveSlots;
-  const WaveTable<V> tab{key, val, A.gamma, A.lds_keys_fit != 0};
-  for (int q = lane; q < kWaveSlots; q += 64) {
-    key[q] = kEmpty;
-    val[q] = V(0);
-  }
+  uint32_t* key = reinterpret_cast<uint32_t*>(lds) + wave * Tab::kLines;
+  V* val = reinterpret_cast<V*>(lds + kWaves * Tab::kLines * sizeof(uint32_t)) +
+           wave * Tab::kLines * kLine;
+  const Tab tab{key, val, A.gamma, A.lds_keys_fit != 0};
+  for (int q = lane; q < Tab::kLines; q += 64) key[q] = kEmpty;
+  for (int q = lane; q < Tab::kLines * kLine; q += 64) val[q] = V(0);
   __builtin_amdgcn_wave_barrier();
 
   LaneAcc acc;
@@ -490,7 +506,7 @@ __global__ __launch_bounds__(kBlock) void k_march(MarchArgs A) {
   const int64_t claim = A.claim;
   int64_t pool = 0, pool_end = 0;  // wavefront-uniform run of claimed rays
   bool exhausted = total <= 0;
-  int fill = 0;                    // wavefront-uniform occupied table slots
+  int fill = 0;                    // wavefront-uniform occupied line slots
   for (;;) {
     const uint64_t idle = __ballot(!busy);
     const int n_idle = __popcll(idle);
@@ -547,7 +563,7 @@ __global__ __launch_bounds__(kBlock) void k_march(MarchArgs A) {
     if (__popcll(__ballot(pend)) >= 32)
       push_pending(&A.acc->out_count[A.level + 1], A.out, A.out_cap, &A.acc->overflow, lane, pend,
                    p_src, p_pix, p_s, p_w);
-    if (fill >= kFlushAt) {
+    if (fill >= Tab::kFlushAt) {
       tab.flush(lane);
       fill = 0;
     }
@@ -558,8 +574,7 @@ __global__ __launch_bounds__(kBlock) void k_march(MarchArgs A) {
 
   // block reduction of the lane budgets, then one atomic per block and term
   __syncthreads();
-  static_assert(kWaves * kWaveSlots * (sizeof(uint32_t) + sizeof(V)) >= kBlock * 32,
-                "reduction space");
+  static_assert(kWaves * Tab::kWaveBytes >= kBlock * 32, "reduction space");
   double(*red_d)[kBlock] = reinterpret_cast<double(*)[kBlock]>(lds);
   unsigned long long* red_u = reinterpret_cast<unsigned long long*>(lds + 3 * kBlock * 8);
   red_d[0][threadIdx.x] = acc.absorbed;
