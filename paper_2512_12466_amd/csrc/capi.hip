@@ -479,7 +479,7 @@ nrt_status nrt_init_grid(nrt_ctx** out, const nrt_grid_desc* desc, const double*
   if (e == hipSuccess)
     e = hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, c->device);
   if (e == hipSuccess)
-    e = nrt::march_blocks_per_cu(desc->precision == NRT_MIXED, &c->march_blocks_per_cu);
+    e = nrt::march_blocks_per_cu(*desc, &c->march_blocks_per_cu);
   if (e != hipSuccess) return bail(hip_fail(c, e, "device query"));
   const Layout& L = c->lay;
   c->n_H = reinterpret_cast<double*>(c->ws + L.n_H);

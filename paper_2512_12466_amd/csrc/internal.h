@@ -139,7 +139,7 @@ hipError_t launch_prep(nrt_ctx* c);
 hipError_t launch_zero(double* p, int64_t count, int cus, hipStream_t s);
 hipError_t launch_zero_accum(Accum* acc, hipStream_t s);
 hipError_t launch_march(const nrt_ctx* c, const MarchArgs& a, int64_t rays, hipStream_t st);
-hipError_t march_blocks_per_cu(bool mixed, int* blocks);
+hipError_t march_blocks_per_cu(const nrt_grid_desc& d, int* blocks);
 hipError_t launch_healpix(int level, int64_t first, int64_t count, double* out, hipStream_t s);
 
 // merge.hip

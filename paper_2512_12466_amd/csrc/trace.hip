@@ -98,24 +98,45 @@ struct LineTable {
   double* gamma;
   bool on;  // false when line indices do not fit 32 bits below kEmpty
 
-  // returns true if the deposit occupied a new slot
-  __device__ __forceinline__ bool add(int64_t c, V v) const {
+  // First probe for the line of cell c, issued as soon as the cell is known
+  // so that the compare-and-swap is in flight while the step's arithmetic
+  // runs; `deposit` consumes its result.
+  struct Claim {
+    uint32_t k, h, old;
+  };
+  __device__ __forceinline__ Claim claim(int64_t c) const {
+    Claim cl{uint32_t(c >> 3), 0u, 0u};
     if (on) {
-      const uint32_t k = uint32_t(c >> 3);
+      cl.h = (cl.k * 2654435761u) >> (32 - kLog2Lines);
+      cl.old = atomicCAS(&key[cl.h], kEmpty, cl.k);
+    }
+    return cl;
+  }
+  // whether the claim took a new slot (it stays taken even if no value follows)
+  __device__ __forceinline__ static bool took(const Claim& cl) { return cl.old == kEmpty; }
+
+  // add v for cell c to the slot of its claim, probing further if the first
+  // slot belongs to another line
+  __device__ __forceinline__ int deposit(const Claim& cl, int64_t c, V v) const {
+    if (on) {
       const uint32_t sub = uint32_t(c) & uint32_t(kLine - 1);
-      uint32_t h = (k * 2654435761u) >> (32 - kLog2Lines);
+      if (cl.old == kEmpty || cl.old == cl.k) {
+        atomicAdd(&val[cl.h * kLine + sub], v);
+        return 0;
+      }
+      uint32_t h = cl.h;
 #pragma unroll 1
-      for (int probe = 0; probe < kProbe; ++probe) {
-        const uint32_t old = atomicCAS(&key[h], kEmpty, k);
-        if (old == kEmpty || old == k) {
-          atomicAdd(&val[h * kLine + sub], v);
-          return old == kEmpty;
-        }
+      for (int probe = 1; probe < kProbe; ++probe) {
         h = (h + 1) & uint32_t(kLines - 1);
+        const uint32_t old = atomicCAS(&key[h], kEmpty, cl.k);
+        if (old == kEmpty || old == cl.k) {
+          atomicAdd(&val[h * kLine + sub], v);
+          return old == kEmpty ? 1 : 0;
+        }
       }
     }
     atomicAdd(gamma + c, double(v));
-    return false;
+    return 0;
   }
 
   // whole wavefront: fold the table into Gamma and clear it (LDS operations
@@ -166,7 +187,7 @@ struct RayState {
 // Load ray r of the launch (a virtual spawn index, a queue entry or an
 // injected ray) and find its start cell.  Returns kEscaped if it starts
 // outside an open box, else kGoOn.
-template <bool MIXED>
+template <bool MIXED, bool PERIODIC>
 __device__ int ray_init(RayState& R, const MarchArgs& A, int64_t r) {
   double w;
   if (A.level < 0) {  // injected rays: never split
@@ -223,10 +244,10 @@ __device__ int ray_init(RayState& R, const MarchArgs& A, int64_t r) {
   }
   const int n = A.n;
   const bool out = R.i0 < 0 || R.i0 >= n || R.i1 < 0 || R.i1 >= n || R.i2 < 0 || R.i2 >= n;
-  if (!A.periodic && out) return kEscaped;
-  R.w0 = A.periodic ? wrap_cell(R.i0, n) : R.i0;
-  R.w1 = A.periodic ? wrap_cell(R.i1, n) : R.i1;
-  R.w2 = A.periodic ? wrap_cell(R.i2, n) : R.i2;
+  if (!PERIODIC && out) return kEscaped;
+  R.w0 = PERIODIC ? wrap_cell(R.i0, n) : R.i0;
+  R.w1 = PERIODIC ? wrap_cell(R.i1, n) : R.i1;
+  R.w2 = PERIODIC ? wrap_cell(R.i2, n) : R.i2;
   const int64_t n64 = n;
   const int64_t c0 = int64_t(R.w0) + n64 * (int64_t(R.w1) + n64 * int64_t(R.w2));
   if (MIXED)
@@ -243,13 +264,13 @@ __device__ int ray_init(RayState& R, const MarchArgs& A, int64_t r) {
 // slots taken by this call's deposits.  Memory latency is hidden by order:
 // the cell's absorber was loaded at the end of the previous step, and the
 // neighbour's is requested before the attenuation arithmetic that follows.
-template <bool MIXED, typename V>
+template <bool MIXED, int CORR, bool PERIODIC, typename V>
 __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab, LaneAcc& acc,
                         int& inserted) {
   const int n = A.n;
   const int64_t n64 = n;
-  const bool open_box = !A.periodic;
-  if (A.periodic && R.s >= A.s_max) return kEscaped;
+  constexpr bool open_box = !PERIODIC;
+  if (PERIODIC && R.s >= A.s_max) return kEscaped;
   if (MIXED ? (R.T <= A.t_min) : (R.tau >= A.tau_max)) return kTruncated;
   if (R.s * R.s > R.r2s) return R.level >= A.l_max ? kTruncated : kSplit;
   // next crossing: lowest axis wins exact ties
@@ -266,6 +287,8 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab
   double ds = tn - R.s;
   if (ds < 0.0) ds = 0.0;
   const int64_t c = int64_t(R.w0) + n64 * (int64_t(R.w1) + n64 * int64_t(R.w2));
+  const auto cl1 = tab.claim(c);
+  typename LineTable<V>::Claim cl2{0u, 0u, 0u};
 
   // ---- overlap geometry (Eqs. correction .. new_secondary): nearest face
   // of the segment midpoint, and the neighbour across it ----
@@ -275,7 +298,7 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab
   int64_t c2 = 0;
   double raw2_64 = 0.0;
   float raw2_32 = 0.0f;
-  if (A.corr != NRT_CORR_NONE) {
+  if constexpr (CORR != NRT_CORR_NONE) {
     const double rm = 0.5 * (R.s + tn);
     lpix = rm * R.sqo;
     int fax = 0, fdir;
@@ -306,7 +329,7 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab
       }
     }
     near = dedge < 0.5 * lpix;
-    if (near && (A.corr == NRT_CORR_CONSERVATIVE || A.corr == NRT_CORR_NAIVE)) {
+    if (near && (CORR == NRT_CORR_CONSERVATIVE || CORR == NRT_CORR_NAIVE)) {
       const int j0 = R.i0 + (fax == 0 ? fdir : 0);
       const int j1 = R.i1 + (fax == 1 ? fdir : 0);
       const int j2 = R.i2 + (fax == 2 ? fdir : 0);
@@ -317,6 +340,7 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab
         const int v2 = fax == 2 ? (open_box ? j2 : wrap_step(R.w2, fdir, n)) : R.w2;
         c2 = int64_t(v0) + n64 * (int64_t(v1) + n64 * int64_t(v2));
         neighbour = true;
+        cl2 = tab.claim(c2);
         if (MIXED)
           raw2_32 = A.a32[c2];
         else
@@ -379,11 +403,11 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab
       f = 0.5f + float(dedge) * __builtin_amdgcn_rcpf(float(lpix));
     else
       f = 0.5 + dedge / lpix;
-    if (A.corr == NRT_CORR_LINEAR) {
+    if constexpr (CORR == NRT_CORR_LINEAR) {
       fc = f;
-    } else if (A.corr == NRT_CORR_SQUARED) {
+    } else if constexpr (CORR == NRT_CORR_SQUARED) {
       fc = f * f;
-    } else if (A.corr == NRT_CORR_CONSERVATIVE) {
+    } else if constexpr (CORR == NRT_CORR_CONSERVATIVE) {
       if (usable) fc = f;
       secondary = usable;
     } else {  // NAIVE
@@ -393,13 +417,15 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab
   }
 
   // ---- deposit ----
+  inserted += LineTable<V>::took(cl1) ? 1 : 0;
+  if (neighbour) inserted += LineTable<V>::took(cl2) ? 1 : 0;
   if constexpr (MIXED) {
-    inserted += tab.add(c, fc * G32) ? 1 : 0;
+    inserted += tab.deposit(cl1, c, fc * G32);
     if (secondary)
-      inserted += tab.add(c2, ((1.0f - fc) * (a32 * __builtin_amdgcn_rcpf(raw2_32))) * G32) ? 1 : 0;
+      inserted += tab.deposit(cl2, c2, ((1.0f - fc) * (a32 * __builtin_amdgcn_rcpf(raw2_32))) * G32);
   } else {
-    inserted += tab.add(c, fc * G64) ? 1 : 0;
-    if (secondary) inserted += tab.add(c2, ((1.0 - fc) * (a64 / raw2_64)) * G64) ? 1 : 0;
+    inserted += tab.deposit(cl1, c, fc * G64);
+    if (secondary) inserted += tab.deposit(cl2, c2, ((1.0 - fc) * (a64 / raw2_64)) * G64);
   }
 
   // ---- advance one cell: step the winning axis (its component is nonzero)
@@ -475,7 +501,7 @@ __device__ __forceinline__ void push_pending(unsigned long long* count, const Ra
 // children's start state in registers; the wavefront appends the children of
 // all pending splits to the next level's queue with one atomicAdd once 32 are
 // pending (or a pending lane splits again, or the run ends).
-template <bool MIXED>
+template <bool MIXED, int CORR, bool PERIODIC>
 __global__ __launch_bounds__(kBlock) void k_march(MarchArgs A) {
   using V = typename std::conditional<MIXED, float, double>::type;
   // per-wavefront deposit tables, reused for the budget reduction at the end
@@ -526,7 +552,7 @@ __global__ __launch_bounds__(kBlock) void k_march(MarchArgs A) {
         const int64_t avail = pool_end - pool;
         const unsigned rank = lanes_below(idle);
         if (!busy && int64_t(rank) < avail) {
-          const int start = ray_init<MIXED>(R, A, A.begin + pool + rank);
+          const int start = ray_init<MIXED, PERIODIC>(R, A, A.begin + pool + rank);
           busy = start == kGoOn;
           if (!busy) acc.escaped += MIXED ? R.L * R.T : R.P;
         }
@@ -539,7 +565,7 @@ __global__ __launch_bounds__(kBlock) void k_march(MarchArgs A) {
     }
     int code = kGoOn, inserted = 0;
     if (busy) {
-      code = ray_step<MIXED>(R, A, tab, acc, inserted);
+      code = ray_step<MIXED, CORR, PERIODIC>(R, A, tab, acc, inserted);
       if (code != kGoOn) {
         busy = false;
         const double carried = MIXED ? R.L * R.T : R.P;
@@ -548,7 +574,8 @@ __global__ __launch_bounds__(kBlock) void k_march(MarchArgs A) {
         if (MIXED) acc.absorbed += R.L * R.absf;
       }
     }
-    fill += __popcll(__ballot(inserted >= 1)) + __popcll(__ballot(inserted >= 2));
+    fill += __popcll(__ballot(inserted & 1)) + 2 * __popcll(__ballot(inserted & 2)) +
+            4 * __popcll(__ballot(inserted & 4));
     const bool splits = code == kSplit;
     if (__ballot(splits && pend))  // a lane splits again
       push_pending(&A.acc->out_count[A.level + 1], A.out, A.out_cap, &A.acc->overflow, lane, pend,
@@ -672,9 +699,33 @@ hipError_t launch_zero_accum(Accum* acc, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t march_blocks_per_cu(bool mixed, int* blocks) {
-  return mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_march<true>, kBlock, 0)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_march<false>, kBlock, 0);
+namespace {
+
+// the march instantiation for a precision, correction mode and boundary
+using MarchKernel = void (*)(MarchArgs);
+
+template <bool MIXED, bool PERIODIC>
+MarchKernel march_for_corr(int corr) {
+  switch (corr) {
+    case NRT_CORR_NONE: return k_march<MIXED, NRT_CORR_NONE, PERIODIC>;
+    case NRT_CORR_LINEAR: return k_march<MIXED, NRT_CORR_LINEAR, PERIODIC>;
+    case NRT_CORR_SQUARED: return k_march<MIXED, NRT_CORR_SQUARED, PERIODIC>;
+    case NRT_CORR_NAIVE: return k_march<MIXED, NRT_CORR_NAIVE, PERIODIC>;
+    default: return k_march<MIXED, NRT_CORR_CONSERVATIVE, PERIODIC>;
+  }
+}
+
+MarchKernel march_kernel(const nrt_grid_desc& d) {
+  const bool mixed = d.precision == NRT_MIXED;
+  if (mixed)
+    return d.periodic ? march_for_corr<true, true>(d.corr) : march_for_corr<true, false>(d.corr);
+  return d.periodic ? march_for_corr<false, true>(d.corr) : march_for_corr<false, false>(d.corr);
+}
+
+}  // namespace
+
+hipError_t march_blocks_per_cu(const nrt_grid_desc& d, int* blocks) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, march_kernel(d), kBlock, 0);
 }
 
 // persistent grid: as many blocks as stay resident, or fewer for small launches
@@ -689,10 +740,7 @@ hipError_t launch_march(const nrt_ctx* c, const MarchArgs& args, int64_t rays, h
   // ray set-up
   a.claim = c->tuning.claim > 0 ? c->tuning.claim : 64;
   a.refill_min = c->tuning.refill_min > 0 ? c->tuning.refill_min : 16;
-  if (c->desc.precision == NRT_MIXED)
-    hipLaunchKernelGGL(k_march<true>, dim3(blocks), dim3(kBlock), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_march<false>, dim3(blocks), dim3(kBlock), 0, st, a);
+  hipLaunchKernelGGL(march_kernel(c->desc), dim3(blocks), dim3(kBlock), 0, st, a);
   return hipGetLastError();
 }
 
