@@ -64,6 +64,18 @@ __device__ __forceinline__ unsigned long long read_lane64(unsigned long long v, 
   return (static_cast<unsigned long long>(hi) << 32) | lo;
 }
 
+// The march's argument block, read through a pointer that the compiler must
+// treat as new at every use: values read this way are re-read from the
+// (scalar-cached) argument segment where they are used instead of being held
+// in scalar registers across the whole loop.  The ray set-up reads its many
+// pointers like this, which leaves the per-step path its registers.
+using ArgsK = const MarchArgs __attribute__((address_space(4)));
+__device__ __forceinline__ ArgsK& fresh_args() {
+  ArgsK* p = (ArgsK*)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(p));
+  return *p;
+}
+
 struct LaneAcc {
   double absorbed = 0.0, escaped = 0.0, truncated = 0.0;
   unsigned long long segments = 0;
@@ -187,8 +199,8 @@ struct RayState {
 // Load ray r of the launch (a virtual spawn index, a queue entry or an
 // injected ray) and find its start cell.  Returns kEscaped if it starts
 // outside an open box, else kGoOn.
-template <bool MIXED, bool PERIODIC>
-__device__ int ray_init(RayState& R, const MarchArgs& A, int64_t r) {
+template <bool MIXED, bool PERIODIC, typename Args>
+__device__ int ray_init(RayState& R, Args& A, int64_t r) {
   double w;
   if (A.level < 0) {  // injected rays: never split
     R.o0 = A.inj_origin[3 * r];
@@ -537,9 +549,10 @@ __global__ __launch_bounds__(kBlock) void k_march(MarchArgs A) {
     const uint64_t idle = __ballot(!busy);
     const int n_idle = __popcll(idle);
     if (!exhausted && (n_idle >= A.refill_min || n_idle == 64)) {
+      ArgsK& F = fresh_args();
       if (pool == pool_end) {
         unsigned long long b = 0;
-        if (lane == 0) b = atomicAdd(A.claim_ctr, static_cast<unsigned long long>(claim));
+        if (lane == 0) b = atomicAdd(F.claim_ctr, static_cast<unsigned long long>(claim));
         b = read_lane64(b, 0);
         if (int64_t(b) >= total) {
           exhausted = true;
@@ -552,7 +565,7 @@ __global__ __launch_bounds__(kBlock) void k_march(MarchArgs A) {
         const int64_t avail = pool_end - pool;
         const unsigned rank = lanes_below(idle);
         if (!busy && int64_t(rank) < avail) {
-          const int start = ray_init<MIXED, PERIODIC>(R, A, A.begin + pool + rank);
+          const int start = ray_init<MIXED, PERIODIC>(R, F, F.begin + pool + rank);
           busy = start == kGoOn;
           if (!busy) acc.escaped += MIXED ? R.L * R.T : R.P;
         }
