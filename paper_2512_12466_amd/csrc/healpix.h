@@ -26,16 +26,17 @@ __device__ __forceinline__ uint32_t hp_compact(uint32_t v) {
   return v;
 }
 
+// level <= 14, pix < 12 * 4^level: every integer below fits 32 bits
 __device__ inline void healpix_dir(int level, uint32_t pix, double& dx, double& dy, double& dz) {
-  const int64_t ns = int64_t(1) << level;
+  const int ns = 1 << level;
   const uint32_t face = pix >> (2 * level);
   const uint32_t ipf = pix - (face << (2 * level));
-  const int64_t ix = hp_compact(ipf);
-  const int64_t iy = hp_compact(ipf >> 1);
-  const int64_t row = face >> 2;  // 0 north, 1 equatorial, 2 south
-  const int64_t jr = (row + 2) * ns - ix - iy - 1;
+  const int ix = int(hp_compact(ipf));
+  const int iy = int(hp_compact(ipf >> 1));
+  const int row = int(face >> 2);  // 0 north, 1 equatorial, 2 south
+  const int jr = (row + 2) * ns - ix - iy - 1;
 
-  int64_t nr;
+  int nr;
   double z, st;
   if (jr < ns) {
     nr = jr;
@@ -53,13 +54,15 @@ __device__ inline void healpix_dir(int level, uint32_t pix, double& dx, double& 
     st = sqrt((1.0 - z) * (1.0 + z));
   }
 
-  const int64_t jpll = 2 * int64_t(face & 3u) + (row == 1 ? 0 : 1);
-  int64_t num = jpll * nr + ix - iy;  // phi = (pi/2) num / (2 nr)
+  const int jpll = 2 * int(face & 3u) + (row == 1 ? 0 : 1);
+  int num = jpll * nr + ix - iy;  // phi = (pi/2) num / (2 nr)
   if (num < 0) num += 8 * nr;
   if (num >= 8 * nr) num -= 8 * nr;
-  const int64_t quad = num / (2 * nr);
-  const int64_t rem = num - quad * 2 * nr;
+  const int quad = int(num >= 2 * nr) + int(num >= 4 * nr) + int(num >= 6 * nr);
+  const int rem = num - quad * 2 * nr;
 
+  // azimuth within the quadrant folded into [0, pi/4]: one cos and one sin
+  // per lane, swapped for the upper half
   double c, s;
   if (rem == 0) {
     c = 1.0;
@@ -67,14 +70,13 @@ __device__ inline void healpix_dir(int level, uint32_t pix, double& dx, double& 
   } else if (rem == nr) {
     c = 0.70710678118654752440;  // sqrt(1/2), correctly rounded
     s = c;
-  } else if (rem < nr) {
-    const double ang = (3.14159265358979323846 * double(rem)) / double(4 * nr);
-    c = cos(ang);
-    s = sin(ang);
   } else {
-    const double ang = (3.14159265358979323846 * double(2 * nr - rem)) / double(4 * nr);
-    c = sin(ang);
-    s = cos(ang);
+    const bool low = rem < nr;
+    const int k = low ? rem : 2 * nr - rem;
+    const double ang = (3.14159265358979323846 * double(k)) / double(4 * nr);
+    const double ca = cos(ang), sa = sin(ang);
+    c = low ? ca : sa;
+    s = low ? sa : ca;
   }
   double cx, sy;
   if (quad == 0) {

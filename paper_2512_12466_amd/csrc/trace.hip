@@ -24,6 +24,14 @@ namespace nrt {
 namespace {
 
 __device__ __forceinline__ int wrap_cell(int i, int n) {
+  // start cells lie within a few box lengths of the box: conditional steps
+  // instead of an integer division
+  if (i >= -2 * n && i < 3 * n) {
+    int r = i < 0 ? i + n : i;
+    r = r < 0 ? r + n : r;
+    r = r >= n ? r - n : r;
+    return r >= n ? r - n : r;
+  }
   const int r = i % n;
   return r < 0 ? r + n : r;
 }
@@ -218,8 +226,14 @@ __device__ int ray_init(RayState& R, Args& A, int64_t r) {
     R.src = R.pix = 0;
   } else {
     if (A.spawn) {
-      R.src = uint32_t(A.src_begin + r / 12);
-      R.pix = uint32_t(r % 12);
+      if (r < (int64_t(1) << 32)) {
+        const uint32_t r32 = uint32_t(r);
+        R.src = uint32_t(A.src_begin) + r32 / 12u;
+        R.pix = r32 % 12u;
+      } else {
+        R.src = uint32_t(A.src_begin + r / 12);
+        R.pix = uint32_t(r % 12);
+      }
       R.s = 0.0;
       w = MIXED ? 1.0 : 0.0;
     } else {
