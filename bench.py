@@ -33,37 +33,76 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+WORKLOADS = {  # name -> generator in workloads/ (configs 1-5 of the method's test ladder)
+    "stromgren-testA-32": "config1",
+    "lognormal-128-64src": "config2",
+    "lognormal-256-4096src-bubbles": "config3",
+    "clustered-512-32768src": "config4",
+    "late-reion-1024-262144src": "config5",
+}
+
+
 def make_workload(name):
     import workloads as W
-    if name == "lognormal-128-64src":
-        return W.config2()
-    if name == "stromgren-testA-32":
-        return W.config1()
-    if name == "lognormal-256-4096src-bubbles":
-        return W.config3()
-    raise SystemExit(f"unknown workload {name}")
+    if name not in WORKLOADS:
+        raise SystemExit(f"unknown workload {name}; one of {sorted(WORKLOADS)}")
+    t0 = time.perf_counter()
+    w = getattr(W, WORKLOADS[name])(**({"log": log} if name.startswith("late-reion") else {}))
+    log(f"generated {w.name}: {w.n}^3, {len(w.ndot)} sources in {time.perf_counter() - t0:.1f} s")
+    return w
 
 
-def run_path(nrt, w, precision, steps, warmup, capacity, graph=0):
+def subset_indices(m, k, seed=11):
+    import numpy as np
+    g = np.random.default_rng(12466 + 950 + seed)
+    return np.sort(g.choice(m, size=k, replace=False))
+
+
+def run_path(nrt, w, precision, steps, warmup, capacity, graph=0, sources=0, tune=False):
+    """Time `steps` trace passes (after `warmup` untimed ones) of one
+    arithmetic path.  Merging workloads merge first (timed on its own); with
+    `sources`, a seeded subset of the (merged) catalogue is traced."""
     import torch
     desc = nrt.make_desc(w.n, w.h_cm, periodic=w.periodic, n_min_ray=w.n_min_ray, l_max=w.l_max,
                          tau_max=w.tau_max, n_th=w.n_th, precision=precision)
     ctx = nrt.init_grid(desc, w.n_H, w.x, device="cuda:0", max_sources=len(w.ndot),
                         ray_capacity=capacity)
     ctx.add_sources(w.pos, w.ndot)
+    merge_ms, m_traced = None, len(w.ndot)
+    if w.merge:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m_traced = ctx.merge_sources()
+        torch.cuda.synchronize()
+        merge_ms = 1e3 * (time.perf_counter() - t0)
+        log(f"merged {len(w.ndot)} -> {m_traced} sources in {merge_ms:.1f} ms")
+    if sources and sources < m_traced:
+        p, f, _ = ctx.get_sources()
+        idx = subset_indices(m_traced, sources)
+        ctx.clear_sources()
+        ctx.add_sources(p[idx], f[idx])
+        m_traced = len(idx)
     ctx.set_tuning(graph=graph)
     gamma = torch.empty((w.n,) * 3, dtype=torch.float64, device="cuda:0")
-    for _ in range(warmup):
+    tuning = None
+    if tune:
+        t = ctx.autotune(passes=1, gamma=gamma)
+        tuning = dict(t)
+        log(f"autotuned: {tuning}")
+    for i in range(warmup):
         _, b = ctx.trace_step(gamma)
+        log(f"  warm-up pass {i + 1}/{warmup}: {b['segments']} segments")
     torch.cuda.synchronize()
     segs, kernel_ms, launches = 0, 0.0, 0
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for i in range(steps):
         _, b = ctx.trace_step(gamma)
         avg, nl = ctx.last_kernel_time()
         kernel_ms += avg * nl
         launches += nl
         segs += b["segments"]
+        if steps > 1 and w.n >= 512:
+            log(f"  pass {i + 1}/{steps}: {time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     graph = ctx.last_pass_was_graph()
@@ -71,7 +110,60 @@ def run_path(nrt, w, precision, steps, warmup, capacity, graph=0):
     return dict(wall_s=wall, steps=steps, ms_per_step=1e3 * wall / steps,
                 segments_per_step=segs // steps,
                 segments_per_s=segs / wall, kernel_ms_total=kernel_ms, launches=launches,
-                avg_launch_ms=kernel_ms / max(launches, 1), budget=b, graph=graph)
+                avg_launch_ms=kernel_ms / max(launches, 1), budget=b, graph=graph, gamma=gamma,
+                merge_ms=merge_ms, sources_traced=m_traced, tuning=tuning)
+
+
+def run_rt(nrt, w, precision, capacity):
+    """The radiation steps of the Stromgren test: each step iterates trace
+    passes and the chemistry update to convergence (nrt_rt_step); returns ms
+    per RT step, iterations, and the final ionized radius against the
+    closed form."""
+    import math
+    import torch
+    alpha = w.extra["alpha_B"] * w.extra["clumping"]
+    dt, nsteps = w.extra["dt_s"], w.extra["steps"]
+    desc = nrt.make_desc(w.n, w.h_cm, periodic=w.periodic, n_min_ray=w.n_min_ray, l_max=w.l_max,
+                         tau_max=w.tau_max, n_th=w.n_th, precision=precision)
+    ctx = nrt.init_grid(desc, w.n_H, w.x, device="cuda:0", max_sources=len(w.ndot),
+                        ray_capacity=capacity)
+    ctx.add_sources(w.pos, w.ndot)
+    iters = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        _, _, it = ctx.rt_step(dt, alpha)
+        iters.append(it)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    x = ctx.get_ionization().double()
+    ctx.destroy()
+    r_s = (3 * w.ndot[0] / (4 * math.pi * alpha * w.n_H.flat[0] ** 2)) ** (1 / 3) / w.h_cm
+    t_rec = 1 / (alpha * w.n_H.flat[0])
+    r_a = r_s * (1 - math.exp(-nsteps * dt / t_rec)) ** (1 / 3)
+    r_n = (3 * float(x.sum()) / (4 * math.pi)) ** (1 / 3)
+    return dict(ms_per_rt_step=1e3 * wall / nsteps, rt_steps=nsteps, iterations=iters,
+                r_ratio=r_n / r_a)
+
+
+def mixed_vs_fp64(mx, f64):
+    """Error of the mixed result against the FP64 one: Gamma relative error
+    where Gamma > 1e-6 max (max and 99.9th percentile), budget terms relative
+    to the emitted rate, and the count differences."""
+    import torch
+    g, r = mx["gamma"], f64["gamma"]
+    mask = r > 1e-6 * r.max()
+    rel = (g[mask] / r[mask] - 1).abs()
+    k = max(1, int(0.999 * rel.numel()))
+    bm, bf = mx["budget"], f64["budget"]
+    e = bf["emitted"]
+    return {"gamma_max_rel": float(rel.max()),
+            "gamma_p999_rel": float(torch.kthvalue(rel.cpu(), k).values),
+            "budget_max_rel": max(abs(bm[t] - bf[t]) / e for t in ("absorbed", "escaped",
+                                                                    "truncated")),
+            "segments_rel": (bm["segments"] - bf["segments"]) / bf["segments"],
+            "rays_rel": (bm["rays"] - bf["rays"]) / max(bf["rays"], 1),
+            "splits_rel": (bm["splits"] - bf["splits"]) / max(bf["splits"], 1)}
 
 
 def roofline(path, res, counters=None):
@@ -221,6 +313,10 @@ def main():
                     help="0: replay the captured pass once eligible (default), 1: never, 2: always")
     ap.add_argument("--summarize-counters", metavar="DIR",
                     help="write the counter summary of a profiler output directory and exit")
+    ap.add_argument("--sources", type=int, default=0,
+                    help="trace a seeded subset of this many (merged) sources")
+    ap.add_argument("--tune", action="store_true",
+                    help="pick launch parameters with nrt_autotune before timing")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -249,7 +345,8 @@ def main():
     res = {}
     for path in args.paths.split(","):
         prec = nrt.MIXED if path == "mixed" else nrt.FP64
-        r = run_path(nrt, w, prec, args.steps, args.warmup, args.capacity, args.graph)
+        r = run_path(nrt, w, prec, args.steps, args.warmup, args.capacity, args.graph,
+                     args.sources, args.tune)
         r["segments_per_s_kernel"] = r["segments_per_step"] * args.steps / (
             r["kernel_ms_total"] / 1e3)
         res[path] = r
@@ -258,6 +355,16 @@ def main():
             f"{r['segments_per_s_kernel'] / 1e9:.3f} Gseg/s in march kernels "
             f"({r['launches'] // args.steps} launches/step, "
             f"{'graph replay' if r['graph'] else 'host-driven'})")
+    err = mixed_vs_fp64(res["mixed"], res["fp64"]) if {"mixed", "fp64"} <= set(res) else None
+    for r in res.values():
+        r.pop("gamma")
+    rt = None
+    if "steps" in w.extra:  # radiation steps with the chemistry iteration
+        rt = {path: run_rt(nrt, w, nrt.MIXED if path == "mixed" else nrt.FP64, args.capacity)
+              for path in res}
+        for path, v in rt.items():
+            log(f"[{path}] {v['ms_per_rt_step']:.2f} ms per RT step, iterations {v['iterations']}, "
+                f"r/r_closed-form {v['r_ratio']:.4f}")
     head = "mixed" if "mixed" in res else next(iter(res))
     h = res[head]
     counters = read_counters()
@@ -273,6 +380,16 @@ def main():
                    "graph": bool(h["graph"])},
         "roofline": roofline(head, h, counters),
     }
+    out["config"]["per_pass"] = {k: h["budget"][k] for k in ("segments", "rays", "splits")}
+    if w.merge or args.sources:
+        out["config"].update(merge=bool(w.merge), merge_ms=h["merge_ms"],
+                             sources_traced=h["sources_traced"])
+    if h["tuning"]:
+        out["config"]["tuning"] = h["tuning"]
+    if err:
+        out["mixed_vs_fp64"] = err
+    if rt:
+        out["rt_steps"] = rt
     for path, r in res.items():
         if path == head:
             continue

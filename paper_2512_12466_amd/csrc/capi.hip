@@ -113,6 +113,8 @@ MarchArgs base_args(const nrt_ctx* c, double* gamma) {
   a.gamma = gamma;
   a.src_pos = c->src_pos;
   a.src_l0 = c->src_l0;
+  a.dirs = c->dirs;
+  a.dir_max_level = c->lay.dir_levels;
   for (int l = 0; l <= nrt::kMaxLevel; ++l) a.sqrt_omega_tab[l] = c->sqrt_omega[l];
   a.acc = c->acc;
   a.lds_keys_fit = ((int64_t(d.n) * d.n * d.n) >> 3 < (int64_t(1) << 32) - 1) ? 1 : 0;
@@ -407,6 +409,9 @@ Layout plan_layout(const nrt_grid_desc& d, int64_t max_sources, int64_t capacity
   off += per_level * size_t(L.levels);
   L.accum = off;
   off = align256(off + sizeof(Accum));
+  L.dir_levels = std::min(d.l_max, nrt::kDirTableMaxLevel);
+  L.dirs = off;
+  off = align256(off + size_t(nrt::dir_table_offset(L.dir_levels + 1)) * 24);
   L.scratch = off;
   // x_avg and x_new of the chemistry; also staging for injected rays and
   // direction queries, hence a 4 MiB floor
@@ -488,6 +493,7 @@ nrt_status nrt_init_grid(nrt_ctx** out, const nrt_grid_desc* desc, const double*
   c->a32 = desc->precision == NRT_MIXED ? reinterpret_cast<float*>(c->ws + L.a) : nullptr;
   c->src_pos = reinterpret_cast<double*>(c->ws + L.srcpos);
   c->src_l0 = reinterpret_cast<double*>(c->ws + L.srcl0);
+  c->dirs = reinterpret_cast<double*>(c->ws + L.dirs);
   char* q = c->ws + L.queues;
   const size_t cap = size_t(L.capacity);
   for (int l = 0; l <= nrt::kMaxLevel; ++l) c->queue[l] = RayQueue{nullptr, nullptr, nullptr, nullptr};
@@ -518,6 +524,10 @@ nrt_status nrt_init_grid(nrt_ctx** out, const nrt_grid_desc* desc, const double*
   if (e != hipSuccess) return bail(hip_fail(c, e, "field copy"));
   st = prep_absorber(c, c->x);
   if (st) return bail(st);
+  for (int l = 0; l <= L.dir_levels && e == hipSuccess; ++l)
+    e = nrt::launch_healpix(l, 0, 12 * (int64_t(1) << (2 * l)), c->dirs + 3 * nrt::dir_table_offset(l),
+                            c->stream);
+  if (e != hipSuccess) return bail(hip_fail(c, e, "direction table"));
   *out = c;
   return NRT_OK;
 }

@@ -56,6 +56,8 @@ struct MarchArgs {
   const float* a32;
   double* gamma;
   // sources
+  const double* dirs;     // HEALPix directions (x, y, z) of levels 0..dir_max_level
+  int32_t dir_max_level;
   const double* src_pos;  // 3 per source
   const double* src_l0;   // rate per level-0 ray (ndot / 12)
   int64_t src_begin;
@@ -79,10 +81,20 @@ struct MarchArgs {
 };
 
 // Workspace carve-out (byte offsets into the caller's buffer).
+// HEALPix directions of every pixel of levels 0..kDirTableMaxLevel are kept
+// in a table (24 B per pixel: 1.6 GB at level 11); deeper levels compute them
+constexpr int kDirTableMaxLevel = 11;
+
+// first table entry of a level: 12 (4^0 + ... + 4^(level-1)) = 4 (4^level - 1)
+__host__ __device__ inline int64_t dir_table_offset(int level) {
+  return 4 * ((int64_t(1) << (2 * level)) - 1);
+}
+
 struct Layout {
-  size_t n_H, x, a, srcpos, srcl0, srcaux, queues, accum, scratch, total;
+  size_t n_H, x, a, srcpos, srcl0, srcaux, queues, accum, dirs, scratch, total;
   int64_t cells, max_sources, capacity;
-  int levels;  // number of level queues (levels 1..l_max)
+  int levels;      // number of level queues (levels 1..l_max)
+  int dir_levels;  // direction table covers levels 0..dir_levels
 };
 
 Layout plan_layout(const nrt_grid_desc& d, int64_t max_sources, int64_t capacity);
@@ -111,6 +123,7 @@ struct nrt_ctx {
   double* x;
   double* a64;
   float* a32;
+  double* dirs;
   double* src_pos;
   double* src_l0;
   nrt::RayQueue queue[nrt::kMaxLevel + 1];

@@ -115,8 +115,7 @@ struct LineTable {
 
   uint32_t* key;  // [kLines] line index (cell >> 3) or kEmpty
   V* val;         // [kLines * kLine] partial sums of the line's cells
-  double* gamma;
-  bool on;  // false when line indices do not fit 32 bits below kEmpty
+  bool on;        // false when line indices do not fit 32 bits below kEmpty
 
   // First probe for the line of cell c, issued as soon as the cell is known
   // so that the compare-and-swap is in flight while the step's arithmetic
@@ -155,7 +154,7 @@ struct LineTable {
         }
       }
     }
-    atomicAdd(gamma + c, double(v));
+    atomicAdd(fresh_args().gamma + c, double(v));
     return 0;
   }
 
@@ -164,6 +163,7 @@ struct LineTable {
   // no deposit hold zero and are skipped, so no address past the grid is
   // formed.
   __device__ __forceinline__ void flush(int lane) const {
+    double* gamma = fresh_args().gamma;
     __builtin_amdgcn_wave_barrier();
     const int sub = lane & (kLine - 1);
     for (int q = lane / kLine; q < kLines; q += 64 / kLine) {
@@ -204,13 +204,51 @@ struct RayState {
   uint32_t src, pix;
 };
 
-// Load ray r of the launch (a virtual spawn index, a queue entry or an
-// injected ray) and find its start cell.  Returns kEscaped if it starts
-// outside an open box, else kGoOn.
+// One ray of a launch as queued: source, HEALPix pixel, path length and
+// carried weight (optical depth in the FP64 path, transmitted fraction in the
+// mixed one).  For injected rays `src` holds the ray's index.
+struct Entry {
+  uint32_t src, pix;
+  double s, w;
+};
+
+// Entry r of the launch: a virtual spawn index, a queue slot or an injected
+// ray's index.
+template <bool MIXED, typename Args>
+__device__ __forceinline__ Entry load_entry(Args& A, int64_t r) {
+  Entry e;
+  if (A.level < 0) {
+    e.src = uint32_t(r);
+    e.pix = 0;
+    e.s = 0.0;
+    e.w = MIXED ? 1.0 : 0.0;
+  } else if (A.spawn) {
+    if (r < (int64_t(1) << 32)) {
+      const uint32_t r32 = uint32_t(r);
+      e.src = uint32_t(A.src_begin) + r32 / 12u;
+      e.pix = r32 % 12u;
+    } else {
+      e.src = uint32_t(A.src_begin + r / 12);
+      e.pix = uint32_t(r % 12);
+    }
+    e.s = 0.0;
+    e.w = MIXED ? 1.0 : 0.0;
+  } else {
+    e.src = A.in.src[r];
+    e.pix = A.in.pix[r];
+    e.s = A.in.s[r];
+    e.w = A.in.w[r];
+  }
+  return e;
+}
+
+// Start the ray of entry e: direction, start cell and first absorber.
+// Returns kEscaped if it starts outside an open box, else kGoOn.
 template <bool MIXED, bool PERIODIC, typename Args>
-__device__ int ray_init(RayState& R, Args& A, int64_t r) {
-  double w;
+__device__ int ray_init(RayState& R, Args& A, const Entry& e) {
+  double w = e.w;
   if (A.level < 0) {  // injected rays: never split
+    const int64_t r = e.src;
     R.o0 = A.inj_origin[3 * r];
     R.o1 = A.inj_origin[3 * r + 1];
     R.o2 = A.inj_origin[3 * r + 2];
@@ -220,34 +258,26 @@ __device__ int ray_init(RayState& R, Args& A, int64_t r) {
     R.L = A.inj_L[r];
     R.level = A.inj_level[r];
     R.s = 0.0;
-    w = MIXED ? 1.0 : 0.0;
     R.r2s = __builtin_inf();
     R.sqo = A.sqrt_omega_tab[R.level];  // by value in the argument block
     R.src = R.pix = 0;
   } else {
-    if (A.spawn) {
-      if (r < (int64_t(1) << 32)) {
-        const uint32_t r32 = uint32_t(r);
-        R.src = uint32_t(A.src_begin) + r32 / 12u;
-        R.pix = r32 % 12u;
-      } else {
-        R.src = uint32_t(A.src_begin + r / 12);
-        R.pix = uint32_t(r % 12);
-      }
-      R.s = 0.0;
-      w = MIXED ? 1.0 : 0.0;
-    } else {
-      R.src = A.in.src[r];
-      R.pix = A.in.pix[r];
-      R.s = A.in.s[r];
-      w = A.in.w[r];
-    }
+    R.src = e.src;
+    R.pix = e.pix;
+    R.s = e.s;
     R.level = A.level;
     R.o0 = A.src_pos[3 * int64_t(R.src)];
     R.o1 = A.src_pos[3 * int64_t(R.src) + 1];
     R.o2 = A.src_pos[3 * int64_t(R.src) + 2];
     R.L = ldexp(A.src_l0[R.src], -2 * R.level);
-    healpix_dir(R.level, R.pix, R.d0, R.d1, R.d2);
+    if (R.level <= A.dir_max_level) {  // the table holds this device function's values
+      const double* d = A.dirs + 3 * (dir_table_offset(R.level) + int64_t(R.pix));
+      R.d0 = d[0];
+      R.d1 = d[1];
+      R.d2 = d[2];
+    } else {
+      healpix_dir(R.level, R.pix, R.d0, R.d1, R.d2);
+    }
     R.r2s = A.r2split;
     R.sqo = A.sqrt_omega;
   }
@@ -538,7 +568,7 @@ __global__ __launch_bounds__(kBlock) void k_march(MarchArgs A) {
   uint32_t* key = reinterpret_cast<uint32_t*>(lds) + wave * Tab::kLines;
   V* val = reinterpret_cast<V*>(lds + kWaves * Tab::kLines * sizeof(uint32_t)) +
            wave * Tab::kLines * kLine;
-  const Tab tab{key, val, A.gamma, A.lds_keys_fit != 0};
+  const Tab tab{key, val, A.lds_keys_fit != 0};
   for (int q = lane; q < Tab::kLines; q += 64) key[q] = kEmpty;
   for (int q = lane; q < Tab::kLines * kLine; q += 64) val[q] = V(0);
   __builtin_amdgcn_wave_barrier();
@@ -579,7 +609,8 @@ __global__ __launch_bounds__(kBlock) void k_march(MarchArgs A) {
         const int64_t avail = pool_end - pool;
         const unsigned rank = lanes_below(idle);
         if (!busy && int64_t(rank) < avail) {
-          const int start = ray_init<MIXED, PERIODIC>(R, F, F.begin + pool + rank);
+          const Entry e = load_entry<MIXED>(F, F.begin + pool + rank);
+          const int start = ray_init<MIXED, PERIODIC>(R, F, e);
           busy = start == kGoOn;
           if (!busy) acc.escaped += MIXED ? R.L * R.T : R.P;
         }
@@ -604,9 +635,12 @@ __global__ __launch_bounds__(kBlock) void k_march(MarchArgs A) {
     fill += __popcll(__ballot(inserted & 1)) + 2 * __popcll(__ballot(inserted & 2)) +
             4 * __popcll(__ballot(inserted & 4));
     const bool splits = code == kSplit;
-    if (__ballot(splits && pend))  // a lane splits again
-      push_pending(&A.acc->out_count[A.level + 1], A.out, A.out_cap, &A.acc->overflow, lane, pend,
+    if (__ballot(splits && pend)) {  // a lane splits again
+      ArgsK& F = fresh_args();
+      const RayQueue out{F.out.src, F.out.pix, F.out.s, F.out.w};
+      push_pending(&F.acc->out_count[F.level + 1], out, F.out_cap, &F.acc->overflow, lane, pend,
                    p_src, p_pix, p_s, p_w);
+    }
     if (splits) {
       pend = true;
       p_src = R.src;
@@ -614,9 +648,12 @@ __global__ __launch_bounds__(kBlock) void k_march(MarchArgs A) {
       p_s = R.s;
       p_w = MIXED ? R.T : R.tau;
     }
-    if (__popcll(__ballot(pend)) >= 32)
-      push_pending(&A.acc->out_count[A.level + 1], A.out, A.out_cap, &A.acc->overflow, lane, pend,
+    if (__popcll(__ballot(pend)) >= 32) {
+      ArgsK& F = fresh_args();
+      const RayQueue out{F.out.src, F.out.pix, F.out.s, F.out.w};
+      push_pending(&F.acc->out_count[F.level + 1], out, F.out_cap, &F.acc->overflow, lane, pend,
                    p_src, p_pix, p_s, p_w);
+    }
     if (fill >= Tab::kFlushAt) {
       tab.flush(lane);
       fill = 0;

@@ -42,9 +42,13 @@ def test_status_strings_and_workspace_plan():
     b32 = nrt.workspace_bytes(dm, 100, 1 << 16)
     cells = 32 ** 3
     assert b64 - b32 == cells * 4  # the mixed path keeps an FP32 absorber
-    # queues: levels 1..l_max, 24 bytes per slot
+    # queues: levels 1..l_max, 24 bytes per slot; direction table: 24 bytes
+    # per pixel of levels 0..min(l_max, 11)
     d2 = nrt.make_desc(32, 1e20, l_max=8)
-    assert nrt.workspace_bytes(d2, 100, 1 << 16) - b64 == 24 * (1 << 16)
+    assert nrt.workspace_bytes(d2, 100, 1 << 16) - b64 == 24 * (1 << 16) + 24 * 12 * 4 ** 8
+    d11, d12 = nrt.make_desc(32, 1e20, l_max=11), nrt.make_desc(32, 1e20, l_max=12)
+    assert (nrt.workspace_bytes(d12, 100, 1 << 16) - nrt.workspace_bytes(d11, 100, 1 << 16)
+            == 24 * (1 << 16))
 
 
 @pytest.mark.parametrize("field,value", [("n", 0), ("h_cm", -1.0), ("l_max", 15),

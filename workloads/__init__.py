@@ -42,26 +42,35 @@ def rng(cfg: int, stream: int) -> np.random.Generator:
     return np.random.default_rng(SEED_BASE + 100 * cfg + stream)
 
 
-def gaussian_field(n: int, gen: np.random.Generator, slope: float = -2.0) -> np.ndarray:
+def gaussian_field(n: int, gen: np.random.Generator, slope: float = -2.0,
+                   log=None) -> np.ndarray:
     """Periodic Gaussian random field with power spectrum P(k) ~ k^slope,
     zero mean, unit variance, shape (n,n,n) indexed [k,j,i]."""
+    log = log or (lambda *a: None)
     white = gen.standard_normal((n, n, n))
     fk = np.fft.rfftn(white)
+    del white
+    log("gaussian field: forward FFT done")
     kx = np.fft.fftfreq(n) * n
     kz = np.fft.rfftfreq(n) * n
-    k2 = kx[:, None, None] ** 2 + kx[None, :, None] ** 2 + kz[None, None, :] ** 2
-    with np.errstate(divide="ignore"):
-        amp = np.where(k2 > 0, k2 ** (slope / 4.0), 0.0)   # sqrt(P) = k^(slope/2)
-    fk *= amp
+    # sqrt(P) = k^(slope/2), applied one slab of the first axis at a time
+    # (the same elementwise operations as on the whole array, less memory)
+    for a in range(n):
+        k2 = kx[a] ** 2 + kx[:, None] ** 2 + kz[None, :] ** 2
+        with np.errstate(divide="ignore"):
+            fk[a] *= np.where(k2 > 0, k2 ** (slope / 4.0), 0.0)
+    log("gaussian field: spectrum applied")
     g = np.fft.irfftn(fk, s=(n, n, n), axes=(0, 1, 2))
+    del fk
+    log("gaussian field: inverse FFT done")
     g -= g.mean()
     g /= g.std()
     return g
 
 
-def lognormal_density(n: int, mean: float, sigma_ln: float, gen) -> np.ndarray:
+def lognormal_density(n: int, mean: float, sigma_ln: float, gen, log=None) -> np.ndarray:
     """n_H = mean * exp(sigma g - sigma^2 / 2): lognormal with the given mean."""
-    g = gaussian_field(n, gen)
+    g = gaussian_field(n, gen, log=log)
     return mean * np.exp(sigma_ln * g - 0.5 * sigma_ln ** 2)
 
 
@@ -99,6 +108,10 @@ def paint_bubbles(n: int, centres: np.ndarray, radii: np.ndarray, x_in: float = 
             ii = [v[(v >= 0) & (v < n)] for v in ii]
         d = [(v + 0.5 - c[a]) ** 2 for a, v in enumerate(ii)]
         inside = (d[2][:, None, None] + d[1][None, :, None] + d[0][None, None, :]) <= r * r
+        if all(v.size and v[0] >= 0 and v[-1] < n for v in ii):  # no wrap: plain slices
+            view = x[ii[2][0]:ii[2][-1] + 1, ii[1][0]:ii[1][-1] + 1, ii[0][0]:ii[0][-1] + 1]
+            view[inside] = x_in
+            continue
         kk, jj, iq = [v % n for v in (ii[2], ii[1], ii[0])]
         sub = x[np.ix_(kk, jj, iq)]
         sub[inside] = x_in
@@ -106,15 +119,21 @@ def paint_bubbles(n: int, centres: np.ndarray, radii: np.ndarray, x_in: float = 
     return x
 
 
-def _ionized_volume(n, centres, radii, gen, samples=400000):
-    """Monte-Carlo estimate of the volume share inside any bubble (periodic)."""
+def _radius_scale(n, centres, u, share, gen, samples=400000, log=None):
+    """Smallest rho with bubbles of radii rho*u covering `share` of the
+    volume, from a Monte-Carlo sample of cell centres: a sample point lies
+    in some bubble iff min_b d_b / u_b <= rho (periodic min-image distance
+    d_b), so the covered share at rho is the share of points whose minimum
+    is at most rho, and rho is that minimum's `share`-quantile."""
     pts = np.floor(gen.random((samples, 3)) * n) + 0.5
-    inside = np.zeros(samples, bool)
-    for c, r in zip(centres, radii):
+    q = np.full(samples, np.inf)
+    for b, (c, ub) in enumerate(zip(np.asarray(centres, float), np.asarray(u, float))):
         d = np.abs(pts - c)
         d = np.minimum(d, n - d)
-        inside |= (d * d).sum(1) <= r * r
-    return inside.mean()
+        np.minimum(q, np.sqrt((d * d).sum(1)) / ub, out=q)
+        if log and (b + 1) % 1000 == 0:
+            log(f"radius scale: {b + 1} bubbles")
+    return float(np.quantile(q, share, method="inverted_cdf"))
 
 
 @dataclass
@@ -198,28 +217,27 @@ def config4(n: int = 512, n_clusters: int = 512, per_cluster: int = 64,
 
 
 def config5(n: int = 1024, n_clusters: int = 4096, per_cluster: int = 64,
-            n_bubbles: int = 5000, target: float = 0.70) -> Workload:
+            n_bubbles: int = 5000, target: float = 0.70, log=None) -> Workload:
     """1024^3 lognormal (ln-sigma 1.5), 4096 clusters x 64 sources, 5000
     bubbles (4096 on cluster centres + 904 uniform) with r = rho U[0.5,1.5],
-    rho bisected to the target ionized volume share; merging on."""
+    rho chosen so that the bubbles cover the target ionized volume share;
+    merging on.  `log` (optional) receives a line per generation phase."""
+    log = log or (lambda *a: None)
     h = L_BOX_COSMO_CM / n
-    nH = lognormal_density(n, NH_COSMO, 1.5, rng(5, 0))
+    nH = lognormal_density(n, NH_COSMO, 1.5, rng(5, 0), log=log)
+    log("config5: density done")
     pos, centres = clustered_cells(n, n_clusters, per_cluster, 2.0, rng(5, 1))
     ndot = lognormal_values(pos.shape[0], 1e50, 2.0, rng(5, 2))
     g = rng(5, 3)
     extra_c = g.random((n_bubbles - n_clusters, 3)) * n
     bc = np.concatenate([centres, extra_c])
     u = g.uniform(0.5, 1.5, size=bc.shape[0])
-    lo, hi = 1.0, 0.25 * n
-    for _ in range(30):
-        mid = 0.5 * (lo + hi)
-        f = _ionized_volume(n, bc, mid * u, np.random.default_rng(SEED_BASE + 599))
-        if f < target:
-            lo = mid
-        else:
-            hi = mid
-    rho = 0.5 * (lo + hi)
-    x = paint_bubbles(n, bc, rho * u)
+    rho = _radius_scale(n, bc, u, target, np.random.default_rng(SEED_BASE + 599), log=log)
+    log(f"config5: radius scale {rho:.3f}")
+    x = np.zeros((n, n, n))
+    for k in range(0, bc.shape[0], 1000):
+        paint_bubbles(n, bc[k:k + 1000], rho * u[k:k + 1000], out=x)
+        log(f"config5: painted {min(k + 1000, bc.shape[0])} bubbles")
     return Workload(f"late-reion-{n}-{pos.shape[0]}src", n, h, True, nH, x, pos, ndot,
                     n_min_ray=4.0, l_max=10, tau_max=30.0, n_th=1e-2 * NH_COSMO, merge=True,
                     extra=dict(rho=rho))
