@@ -305,7 +305,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="lognormal-128-64src")
-    ap.add_argument("--capacity", type=int, default=1 << 23)
+    ap.add_argument("--capacity", type=int, default=1 << 25,
+                    help="ray slots per HEALPix level queue (24 B each)")
     ap.add_argument("--paths", default="mixed,fp64")
     ap.add_argument("--cpu-sources", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")

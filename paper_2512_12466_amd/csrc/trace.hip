@@ -799,10 +799,11 @@ hipError_t launch_march(const nrt_ctx* c, const MarchArgs& args, int64_t rays, h
     per_cu = c->tuning.blocks_per_cu;
   const int blocks = grid_for(rays, kBlock, c->cu_count * per_cu);
   MarchArgs a = args;
-  // defaults from a sweep on the 128^3 lognormal workload: one wavefront of
-  // rays per claim balances best; a refill once 16 lanes idle amortizes the
-  // ray set-up
-  a.claim = c->tuning.claim > 0 ? c->tuning.claim : 64;
+  // defaults from sweeps of the device-driven pass on the 128^3, 256^3 and
+  // 512^3 workloads: runs of two wavefronts of rays halve the claims of
+  // short-ray workloads without starving waves at the end of a level; a
+  // refill once 16 lanes idle amortizes the ray set-up
+  a.claim = c->tuning.claim > 0 ? c->tuning.claim : 128;
   a.refill_min = c->tuning.refill_min > 0 ? c->tuning.refill_min : 16;
   hipLaunchKernelGGL(march_kernel(c->desc), dim3(blocks), dim3(kBlock), 0, st, a);
   return hipGetLastError();
