@@ -240,7 +240,7 @@ def summarize_counters(d, out):
         rows = collections.defaultdict(dict)
         for r in csv.DictReader(open(os.path.join(d, name))):
             k = r["Kernel_Name"]
-            key = ("mixed" if "k_march<true>" in k else "fp64" if "k_march<false>" in k
+            key = ("mixed" if "k_march<true" in k else "fp64" if "k_march<false" in k
                    else "copy" if "copyBuffer" in k else None)
             if key:
                 did = int(r["Dispatch_Id"])
