@@ -36,6 +36,14 @@ __device__ __forceinline__ int wrap_cell(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
+// Flat index of the wrapped cell (w0, w1, w2), x fastest.  n <= 4096, so the
+// plane index w1 + n w2 fits 24 bits and one 32 x 32 -> 64 multiply-add
+// finishes the index.
+__device__ __forceinline__ int64_t cell_index(int w0, int w1, int w2, int n) {
+  const uint32_t plane = uint32_t(w1) + __umul24(uint32_t(n), uint32_t(w2));
+  return int64_t(uint64_t(uint32_t(w0)) + uint64_t(uint32_t(n)) * uint64_t(plane));
+}
+
 // one step of a wrapped coordinate
 __device__ __forceinline__ int wrap_step(int w, int step, int n) {
   w += step;
@@ -304,8 +312,7 @@ __device__ int ray_init(RayState& R, Args& A, const Entry& e) {
   R.w0 = PERIODIC ? wrap_cell(R.i0, n) : R.i0;
   R.w1 = PERIODIC ? wrap_cell(R.i1, n) : R.i1;
   R.w2 = PERIODIC ? wrap_cell(R.i2, n) : R.i2;
-  const int64_t n64 = n;
-  const int64_t c0 = int64_t(R.w0) + n64 * (int64_t(R.w1) + n64 * int64_t(R.w2));
+  const int64_t c0 = cell_index(R.w0, R.w1, R.w2, n);
   if (MIXED)
     R.a32 = A.a32[c0];
   else
@@ -324,7 +331,6 @@ template <bool MIXED, int CORR, bool PERIODIC, typename V>
 __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab, LaneAcc& acc,
                         int& inserted) {
   const int n = A.n;
-  const int64_t n64 = n;
   constexpr bool open_box = !PERIODIC;
   if (PERIODIC && R.s >= A.s_max) return kEscaped;
   if (MIXED ? (R.T <= A.t_min) : (R.tau >= A.tau_max)) return kTruncated;
@@ -342,7 +348,7 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab
   }
   double ds = tn - R.s;
   if (ds < 0.0) ds = 0.0;
-  const int64_t c = int64_t(R.w0) + n64 * (int64_t(R.w1) + n64 * int64_t(R.w2));
+  const int64_t c = cell_index(R.w0, R.w1, R.w2, n);
   const auto cl1 = tab.claim(c);
   typename LineTable<V>::Claim cl2{0u, 0u, 0u};
 
@@ -394,7 +400,7 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab
         const int v0 = fax == 0 ? (open_box ? j0 : wrap_step(R.w0, fdir, n)) : R.w0;
         const int v1 = fax == 1 ? (open_box ? j1 : wrap_step(R.w1, fdir, n)) : R.w1;
         const int v2 = fax == 2 ? (open_box ? j2 : wrap_step(R.w2, fdir, n)) : R.w2;
-        c2 = int64_t(v0) + n64 * (int64_t(v1) + n64 * int64_t(v2));
+        c2 = cell_index(v0, v1, v2, n);
         neighbour = true;
         cl2 = tab.claim(c2);
         if (MIXED)
@@ -513,7 +519,7 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab
       (R.i0 < 0 || R.i0 >= n || R.i1 < 0 || R.i1 >= n || R.i2 < 0 || R.i2 >= n))
     return kEscaped;
   // absorber of the next cell, consumed by the next step
-  const int64_t cn = int64_t(R.w0) + n64 * (int64_t(R.w1) + n64 * int64_t(R.w2));
+  const int64_t cn = cell_index(R.w0, R.w1, R.w2, n);
   if (MIXED)
     R.a32 = A.a32[cn];
   else

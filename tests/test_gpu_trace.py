@@ -51,6 +51,32 @@ def run_gpu(gpu, n, h, nH, x, pos, ndot, prec, cap=1 << 18, **kw):
     return out, b
 
 
+BENCH_CAPACITY = 1 << 25  # ray slots per level queue in bench.py
+
+
+def run_gpu_replayed(gpu, w, prec, pos=None, ndot=None, merge=False):
+    """The workload as bench.py times it: 2^25-slot level queues, one eager
+    pass, then the captured device-driven pass replayed; returns the
+    replayed pass's Gamma and budget (and the traced catalogue when merging)."""
+    pos = w.pos if pos is None else pos
+    ndot = w.ndot if ndot is None else ndot
+    desc = gpu.make_desc(w.n, w.h_cm, precision=prec, periodic=w.periodic, n_min_ray=w.n_min_ray,
+                         l_max=w.l_max, tau_max=w.tau_max, n_th=w.n_th)
+    ctx = gpu.init_grid(desc, w.n_H, w.x, device="cuda:0", max_sources=len(ndot),
+                        ray_capacity=BENCH_CAPACITY)
+    ctx.add_sources(pos, ndot)
+    cat = None
+    if merge:
+        ctx.merge_sources(gpu.make_merge_params())
+        cat = ctx.get_sources()
+    g, _ = ctx.trace_step()
+    g, b = ctx.trace_step(g)
+    assert ctx.last_pass_was_graph()
+    out = g.cpu().numpy()
+    ctx.destroy()
+    return out, b, cat
+
+
 def test_device_healpix_matches_oracle(gpu, orc):
     import workloads  # noqa: F401
     n = 4
@@ -211,13 +237,16 @@ def test_full_lognormal_128_fp64_and_mixed(gpu, orc):
     kw = dict(periodic=w.periodic, n_min_ray=w.n_min_ray, l_max=w.l_max, tau_max=w.tau_max,
               n_th=w.n_th)
     ref, rb = orc.trace(orc.make_params(w.n, w.h_cm, **kw), w.n_H, w.x, w.pos, w.ndot)
-    got, b = run_gpu(gpu, w.n, w.h_cm, w.n_H, w.x, w.pos, w.ndot, 0, cap=1 << 22, **kw)
+    got, b, _ = run_gpu_replayed(gpu, w, 0)
     assert rel_err(got, ref)[0] <= 1e-10
     assert b["segments"] == rb["segments"] and b["splits"] == rb["splits"]
     assert budget_err(b, rb) <= 1e-10
-    gm, bm = run_gpu(gpu, w.n, w.h_cm, w.n_H, w.x, w.pos, w.ndot, 1, cap=1 << 22, **kw)
+    gm, bm, _ = run_gpu_replayed(gpu, w, 1)
     assert rel_err(gm, ref)[0] <= 1e-4
     assert budget_err(bm, rb) <= 1e-6
+    # the host-driven chunked pass (small queues) executes the same segments
+    gc, bc = run_gpu(gpu, w.n, w.h_cm, w.n_H, w.x, w.pos, w.ndot, 0, cap=1 << 21, **kw)
+    assert bc["segments"] == rb["segments"] and rel_err(gc, ref)[0] <= 1e-10
     half = len(w.ndot) // 2
     g1, _ = run_gpu(gpu, w.n, w.h_cm, w.n_H, w.x, w.pos[:half], w.ndot[:half], 0, **kw)
     g2, _ = run_gpu(gpu, w.n, w.h_cm, w.n_H, w.x, w.pos[half:], w.ndot[half:], 0, **kw)
@@ -254,15 +283,15 @@ def test_rt_step_stromgren(gpu, orc):
 @pytest.mark.slow
 def test_bubbles_256_4096_sources(gpu, orc):
     """The 256^3 workload with 4096 sources in their own ionized bubbles, at
-    full size in the benchmark's launch configuration: the mixed path against
-    the FP64 path everywhere; both against the oracle on a seeded subset of 64
-    sources (Gamma is additive over sources for a fixed ionization field)."""
+    full size in the benchmark's launch configuration (replayed device-driven
+    pass): the mixed path against the FP64 path everywhere; both against the
+    oracle on a seeded subset of 64 sources (Gamma is additive over sources
+    for a fixed ionization field)."""
     w = W.config3()
     kw = dict(periodic=w.periodic, n_min_ray=w.n_min_ray, l_max=w.l_max, tau_max=w.tau_max,
               n_th=w.n_th)
-    g64, b64 = run_gpu(gpu, w.n, w.h_cm, w.n_H, w.x, w.pos, w.ndot, 0, cap=1 << 23, **kw)
-    gmx, bmx = run_gpu(gpu, w.n, w.h_cm, w.n_H, w.x, w.pos, w.ndot, 1, cap=1 << 23, **kw)
-    assert max(b64["rays_per_level"]) > (1 << 23) // 4  # exercises the chunked levels
+    g64, b64, _ = run_gpu_replayed(gpu, w, 0)
+    gmx, bmx, _ = run_gpu_replayed(gpu, w, 1)
     assert rel_err(gmx, g64)[0] <= 1e-4
     assert budget_err(bmx, b64) <= 1e-6
     for k in ("segments", "rays", "splits"):
@@ -275,6 +304,36 @@ def test_bubbles_256_4096_sources(gpu, orc):
     assert rel_err(gs, ref)[0] <= 1e-10
     assert bs["segments"] == rb["segments"] and bs["splits"] == rb["splits"]
     gm, bm = run_gpu(gpu, w.n, w.h_cm, w.n_H, w.x, s.pos, s.ndot, 1, **kw)
+    assert rel_err(gm, ref)[0] <= 1e-4
+    assert budget_err(bm, rb) <= 1e-6
+
+
+@pytest.mark.slow
+def test_clustered_512_merged(gpu, orc):
+    """The merged 512^3 clustered catalogue (32768 sources) at full size in
+    the benchmark's launch configuration: the GPU's merged catalogue equals
+    the oracle's; the mixed path against the FP64 path over the whole
+    catalogue; both against the oracle on a seeded subset of 64 merged
+    sources."""
+    w = W.config4()
+    kw = dict(periodic=w.periodic, n_min_ray=w.n_min_ray, l_max=w.l_max, tau_max=w.tau_max,
+              n_th=w.n_th)
+    g64, b64, (p, f, _) = run_gpu_replayed(gpu, w, 0, merge=True)
+    gmx, bmx, _ = run_gpu_replayed(gpu, w, 1, merge=True)
+    mc, mf, _ = orc.merge_sources(orc.make_merge_params(), w.n, w.periodic, w.x, w.pos, w.ndot)
+    np.testing.assert_array_equal(np.floor(p).astype(np.int32), mc)
+    np.testing.assert_allclose(f, mf, rtol=1e-13, atol=0)
+    assert rel_err(gmx, g64)[0] <= 1e-4
+    assert budget_err(bmx, b64) <= 1e-6
+    E = b64["emitted"]
+    assert abs(b64["absorbed"] + b64["escaped"] + b64["truncated"] - E) <= 1e-12 * E
+    idx = np.sort(np.random.default_rng(512).choice(len(mf), size=64, replace=False))
+    sp, sf = mc[idx] + 0.5, mf[idx]
+    ref, rb = orc.trace(orc.make_params(w.n, w.h_cm, **kw), w.n_H, w.x, sp, sf)
+    gs, bs = run_gpu(gpu, w.n, w.h_cm, w.n_H, w.x, sp, sf, 0, **kw)
+    assert rel_err(gs, ref)[0] <= 1e-10
+    assert bs["segments"] == rb["segments"] and bs["splits"] == rb["splits"]
+    gm, bm = run_gpu(gpu, w.n, w.h_cm, w.n_H, w.x, sp, sf, 1, **kw)
     assert rel_err(gm, ref)[0] <= 1e-4
     assert budget_err(bm, rb) <= 1e-6
 
