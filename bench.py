@@ -308,7 +308,8 @@ def main():
     ap.add_argument("--capacity", type=int, default=1 << 25,
                     help="ray slots per HEALPix level queue (24 B each)")
     ap.add_argument("--paths", default="mixed,fp64")
-    ap.add_argument("--cpu-sources", type=int, default=8)
+    ap.add_argument("--cpu-sources", type=int, default=64,
+                    help="sources the oracle baseline traces (64: the whole 128^3 pass)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=0, choices=(0, 1, 2),
                     help="0: replay the captured pass once eligible (default), 1: never, 2: always")
