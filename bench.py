@@ -295,8 +295,9 @@ def cpu_baseline(w, sources, threads):
     dt = time.perf_counter() - t0
     return {"value": round(b["segments"] / dt, 1), "unit": "ray-segments/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{len(s.ndot)} of {len(w.ndot)} sources (seeded subset) of {w.name}, "
-                      f"full grid, FP64, {b['segments']} segments in {dt:.1f} s"}
+            "sample": (f"all {len(w.ndot)} sources" if len(s.ndot) == len(w.ndot) else
+                       f"{len(s.ndot)} of {len(w.ndot)} sources (seeded subset)")
+                      + f" of {w.name}, full grid, FP64, {b['segments']} segments in {dt:.1f} s"}
 
 
 def main():
