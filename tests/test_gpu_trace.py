@@ -308,6 +308,39 @@ def test_bubbles_256_4096_sources(gpu, orc):
     assert budget_err(bm, rb) <= 1e-6
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_tuning_changes_only_speed(gpu, orc, prec):
+    """Launch parameters (run size, refill threshold, resident blocks, graph
+    mode) and the autotuner's choice execute the same segments, rays and
+    splits and give the same Gamma (to the summation order of the deposits:
+    1e-12 FP64, FP32 partial sums 2e-5 mixed)."""
+    n = 32
+    nH, x, pos, ndot, h = field_case(n, 77, ionized=0.3, m=5, tau_cell=0.3)
+    kw = dict(periodic=True, n_min_ray=4.0, l_max=7, tau_max=30.0, n_th=4e-4)
+    ref, rb = orc.trace(orc.make_params(n, h, **kw), nH, x, pos, ndot)
+    ctx = gpu.init_grid(gpu.make_desc(n, h, precision=prec, **kw), nH, x, device="cuda:0",
+                        max_sources=8, ray_capacity=1 << 21)
+    ctx.add_sources(pos, ndot)
+    g0, b0 = ctx.trace_step()
+    base = g0.cpu().numpy()
+    assert rel_err(base, ref)[0] <= (1e-10 if prec == 0 else 1e-4)
+    rtol = 1e-12 if prec == 0 else 2e-5
+    for refill, claim, bpc, graph in [(1, 64, 1, 1), (64, 65536, 0, 1), (8, 256, 2, 2),
+                                      (32, 1024, 0, 0), (0, 0, 0, 0)]:
+        ctx.set_tuning(refill, claim, bpc, graph)
+        for _ in range(2):  # the second pass may replay a captured graph
+            g, b = ctx.trace_step(g0)
+            for k in ("segments", "rays", "splits", "rays_per_level"):
+                assert b[k] == b0[k], (refill, claim, bpc, graph, k)
+            np.testing.assert_allclose(g.cpu().numpy(), base, rtol=rtol, atol=1e-14 * base.max())
+    best = ctx.autotune(passes=1, gamma=g0)
+    assert set(best) == {"refill_min", "claim", "blocks_per_cu", "graph"}
+    g, b = ctx.trace_step(g0)
+    assert b["segments"] == b0["segments"]
+    np.testing.assert_allclose(g.cpu().numpy(), base, rtol=rtol, atol=1e-14 * base.max())
+    ctx.destroy()
+
+
 @pytest.mark.slow
 def test_clustered_512_merged(gpu, orc):
     """The merged 512^3 clustered catalogue (32768 sources) at full size in
