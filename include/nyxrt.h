@@ -188,9 +188,12 @@ nrt_status nrt_healpix_dirs(nrt_ctx* ctx, int32_t level, int64_t first, int64_t 
 
 /* Launch parameters of the march kernel.  0 selects the built-in default. */
 typedef struct {
-  int32_t refill_min;    /* idle lanes that make a wavefront fetch new rays (1..64) */
-  int32_t claim;         /* rays a wavefront claims at a time (64..65536, multiple of 64) */
-  int32_t blocks_per_cu; /* resident 256-thread blocks per compute unit               */
+  int32_t refill_min;    /* idle lanes that make a wavefront fetch new rays (1..64;
+                            default 16)                                              */
+  int32_t claim;         /* rays a wavefront claims at a time (64..65536, multiple of
+                            64; default 128)                                         */
+  int32_t blocks_per_cu; /* resident 256-thread blocks per compute unit (default: as
+                            many as the kernel's registers and LDS allow)            */
   int32_t graph;         /* 0: replay a captured device-driven pass (hipGraph) once a
                             pass has shown that every HEALPix level fits its queue;
                             1: never; 2: always try (falls back on overflow)        */

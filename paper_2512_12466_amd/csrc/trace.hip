@@ -9,10 +9,11 @@
 // each lane's slot from a masked lane count.
 //
 // Decisions (next cell, split, stop tests, face of the overlap correction)
-// are FP64 in both instantiations and use only correctly rounded + - * /
-// (the library is compiled with FP contraction off).  MIXED = true computes
-// the optical depth, attenuation and deposits in FP32 from an FP32 absorber
-// and tracks the transmitted fraction in FP64.
+// are FP64 in both precisions and use only correctly rounded + - * / (the
+// library is compiled with FP contraction off).  MIXED = true computes the
+// optical depth, attenuation and deposits in FP32 from an FP32 absorber and
+// tracks the transmitted fraction in FP64.  The march is instantiated per
+// precision, correction mode and boundary.
 #include <cfloat>
 #include <type_traits>
 
