@@ -146,6 +146,47 @@ def run_rt(nrt, w, precision, capacity):
                 r_ratio=r_n / r_a)
 
 
+CORR_MODES = {"none": 0, "linear": 1, "conservative": 2, "squared": 3, "naive": 4}
+
+
+def corr_study(nrt, w, precision, capacity):
+    """The overlap-correction variants on the Stromgren test: per mode, the
+    numerical ionized radius over the closed form after every radiation
+    step, and on the final state one trace pass's deposited photons
+    (sum of Gamma a h^3) over its absorbed photons (1 for a photon-conserving
+    scheme)."""
+    import math
+    import torch
+    alpha = w.extra["alpha_B"] * w.extra["clumping"]
+    dt, nsteps = w.extra["dt_s"], w.extra["steps"]
+    n_h = float(w.n_H.flat[0])
+    r_s = (3 * w.ndot[0] / (4 * math.pi * alpha * n_h ** 2)) ** (1 / 3) / w.h_cm
+    t_rec = 1 / (alpha * n_h)
+    nh_dev = torch.from_numpy(w.n_H).to("cuda:0")
+    out = {}
+    for name, corr in CORR_MODES.items():
+        desc = nrt.make_desc(w.n, w.h_cm, periodic=w.periodic, n_min_ray=w.n_min_ray,
+                             l_max=w.l_max, tau_max=w.tau_max, n_th=w.n_th, corr=corr,
+                             precision=precision)
+        ctx = nrt.init_grid(desc, w.n_H, w.x, device="cuda:0", max_sources=len(w.ndot),
+                            ray_capacity=capacity)
+        ctx.add_sources(w.pos, w.ndot)
+        ratios = []
+        for step in range(1, nsteps + 1):
+            ctx.rt_step(dt, alpha)
+            x = ctx.get_ionization().double()
+            r_n = (3 * float(x.sum()) / (4 * math.pi)) ** (1 / 3)
+            ratios.append(round(r_n / (r_s * (1 - math.exp(-step * dt / t_rec)) ** (1 / 3)), 5))
+        g, b = ctx.trace_step()
+        deposited = float((g * (1 - x) * nh_dev).sum()) * w.h_cm ** 3
+        out[name] = {"r_ratio": ratios, "deposited_over_absorbed": deposited / b["absorbed"],
+                     "absorbed_over_emitted": b["absorbed"] / b["emitted"]}
+        log(f"[{name}] r/r_closed-form {ratios[-1]:.4f}, deposited/absorbed "
+            f"{deposited / b['absorbed']:.6f}")
+        ctx.destroy()
+    return out
+
+
 def mixed_vs_fp64(mx, f64):
     """Error of the mixed result against the FP64 one: Gamma relative error
     where Gamma > 1e-6 max (max and 99.9th percentile), budget terms relative
@@ -318,6 +359,8 @@ def main():
                     help="write the counter summary of a profiler output directory and exit")
     ap.add_argument("--sources", type=int, default=0,
                     help="trace a seeded subset of this many (merged) sources")
+    ap.add_argument("--corr-study", action="store_true",
+                    help="compare the overlap-correction modes on the Stromgren workload and exit")
     ap.add_argument("--tune", action="store_true",
                     help="pick launch parameters with nrt_autotune before timing")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -345,6 +388,14 @@ def main():
         log(f"calibration copy: 3 x {args.calibrate_copy} MiB")
         del src, dst
     w = make_workload(args.workload)
+    if args.corr_study:
+        if "steps" not in w.extra:
+            raise SystemExit("--corr-study needs a workload with radiation steps "
+                             "(stromgren-testA-32)")
+        print(json.dumps({"workload": w.name, "corr_study": {
+            p: corr_study(nrt, w, nrt.MIXED if p == "mixed" else nrt.FP64, args.capacity)
+            for p in args.paths.split(",")}}), flush=True)
+        return
     res = {}
     for path in args.paths.split(","):
         prec = nrt.MIXED if path == "mixed" else nrt.FP64
