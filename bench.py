@@ -114,36 +114,46 @@ def run_path(nrt, w, precision, steps, warmup, capacity, graph=0, sources=0, tun
                 merge_ms=merge_ms, sources_traced=m_traced, tuning=tuning)
 
 
-def run_rt(nrt, w, precision, capacity):
-    """The radiation steps of the Stromgren test: each step iterates trace
-    passes and the chemistry update to convergence (nrt_rt_step); returns ms
-    per RT step, iterations, and the final ionized radius against the
-    closed form."""
+def run_rt(nrt, w, precision, capacity, steps=0, dt_myr=0.0):
+    """Radiation steps: each iterates trace passes and the chemistry update to
+    convergence (nrt_rt_step).  The Stromgren workload uses its own step
+    count and Delta t and reports the final ionized radius against the closed
+    form; other workloads take `steps` steps of `dt_myr` Myr from their
+    initial ionization with case-B recombination at 10^4 K."""
     import math
     import torch
-    alpha = w.extra["alpha_B"] * w.extra["clumping"]
-    dt, nsteps = w.extra["dt_s"], w.extra["steps"]
+    import workloads as W
+    stromgren = "steps" in w.extra
+    alpha = w.extra["alpha_B"] * w.extra["clumping"] if stromgren else W.ALPHA_B_1E4K
+    dt = w.extra["dt_s"] if stromgren else dt_myr * W.MYR_S
+    nsteps = w.extra["steps"] if stromgren else steps
     desc = nrt.make_desc(w.n, w.h_cm, periodic=w.periodic, n_min_ray=w.n_min_ray, l_max=w.l_max,
                          tau_max=w.tau_max, n_th=w.n_th, precision=precision)
     ctx = nrt.init_grid(desc, w.n_H, w.x, device="cuda:0", max_sources=len(w.ndot),
                         ray_capacity=capacity)
     ctx.add_sources(w.pos, w.ndot)
+    if w.merge:
+        ctx.merge_sources()
     iters = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(nsteps):
+    for k in range(nsteps):
         _, _, it = ctx.rt_step(dt, alpha)
         iters.append(it)
+        if not stromgren:
+            log(f"  RT step {k + 1}/{nsteps}: {it} iterations, {time.perf_counter() - t0:.2f} s")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     x = ctx.get_ionization().double()
     ctx.destroy()
-    r_s = (3 * w.ndot[0] / (4 * math.pi * alpha * w.n_H.flat[0] ** 2)) ** (1 / 3) / w.h_cm
-    t_rec = 1 / (alpha * w.n_H.flat[0])
-    r_a = r_s * (1 - math.exp(-nsteps * dt / t_rec)) ** (1 / 3)
-    r_n = (3 * float(x.sum()) / (4 * math.pi)) ** (1 / 3)
-    return dict(ms_per_rt_step=1e3 * wall / nsteps, rt_steps=nsteps, iterations=iters,
-                r_ratio=r_n / r_a)
+    out = dict(ms_per_rt_step=1e3 * wall / nsteps, rt_steps=nsteps, dt_s=dt, iterations=iters,
+               ionized_volume=float(x.mean()))
+    if stromgren:
+        n_h = float(w.n_H.flat[0])
+        r_s = (3 * w.ndot[0] / (4 * math.pi * alpha * n_h ** 2)) ** (1 / 3) / w.h_cm
+        r_a = r_s * (1 - math.exp(-nsteps * dt / (1 / (alpha * n_h)))) ** (1 / 3)
+        out["r_ratio"] = (3 * float(x.sum()) / (4 * math.pi)) ** (1 / 3) / r_a
+    return out
 
 
 CORR_MODES = {"none": 0, "linear": 1, "conservative": 2, "squared": 3, "naive": 4}
@@ -359,6 +369,10 @@ def main():
                     help="write the counter summary of a profiler output directory and exit")
     ap.add_argument("--sources", type=int, default=0,
                     help="trace a seeded subset of this many (merged) sources")
+    ap.add_argument("--rt-steps", type=int, default=0,
+                    help="also time this many radiation steps (trace + chemistry iteration)")
+    ap.add_argument("--rt-dt-myr", type=float, default=0.1,
+                    help="radiation step length for --rt-steps, in Myr")
     ap.add_argument("--corr-study", action="store_true",
                     help="compare the overlap-correction modes on the Stromgren workload and exit")
     ap.add_argument("--tune", action="store_true",
@@ -413,12 +427,13 @@ def main():
     for r in res.values():
         r.pop("gamma")
     rt = None
-    if "steps" in w.extra:  # radiation steps with the chemistry iteration
-        rt = {path: run_rt(nrt, w, nrt.MIXED if path == "mixed" else nrt.FP64, args.capacity)
+    if "steps" in w.extra or args.rt_steps:  # radiation steps with the chemistry iteration
+        rt = {path: run_rt(nrt, w, nrt.MIXED if path == "mixed" else nrt.FP64, args.capacity,
+                           args.rt_steps, args.rt_dt_myr)
               for path in res}
         for path, v in rt.items():
-            log(f"[{path}] {v['ms_per_rt_step']:.2f} ms per RT step, iterations {v['iterations']}, "
-                f"r/r_closed-form {v['r_ratio']:.4f}")
+            log(f"[{path}] {v['ms_per_rt_step']:.2f} ms per RT step, iterations {v['iterations']}"
+                + (f", r/r_closed-form {v['r_ratio']:.4f}" if "r_ratio" in v else ""))
     head = "mixed" if "mixed" in res else next(iter(res))
     h = res[head]
     counters = read_counters()
