@@ -114,7 +114,7 @@ def run_path(nrt, w, precision, steps, warmup, capacity, graph=0, sources=0, tun
                 merge_ms=merge_ms, sources_traced=m_traced, tuning=tuning)
 
 
-def run_rt(nrt, w, precision, capacity, steps=0, dt_myr=0.0):
+def run_rt(nrt, w, precision, capacity, steps=0, dt_myr=0.0, conv_frac=0.0):
     """Radiation steps: each iterates trace passes and the chemistry update to
     convergence (nrt_rt_step).  The Stromgren workload uses its own step
     count and Delta t and reports the final ionized radius against the closed
@@ -138,7 +138,7 @@ def run_rt(nrt, w, precision, capacity, steps=0, dt_myr=0.0):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(nsteps):
-        _, _, it = ctx.rt_step(dt, alpha)
+        _, _, it = ctx.rt_step(dt, alpha, conv_frac=conv_frac)
         iters.append(it)
         if not stromgren:
             log(f"  RT step {k + 1}/{nsteps}: {it} iterations, {time.perf_counter() - t0:.2f} s")
@@ -147,7 +147,7 @@ def run_rt(nrt, w, precision, capacity, steps=0, dt_myr=0.0):
     x = ctx.get_ionization().double()
     ctx.destroy()
     out = dict(ms_per_rt_step=1e3 * wall / nsteps, rt_steps=nsteps, dt_s=dt, iterations=iters,
-               ionized_volume=float(x.mean()))
+               conv_frac=conv_frac, ionized_volume=float(x.mean()))
     if stromgren:
         n_h = float(w.n_H.flat[0])
         r_s = (3 * w.ndot[0] / (4 * math.pi * alpha * n_h ** 2)) ** (1 / 3) / w.h_cm
@@ -373,6 +373,8 @@ def main():
                     help="also time this many radiation steps (trace + chemistry iteration)")
     ap.add_argument("--rt-dt-myr", type=float, default=0.1,
                     help="radiation step length for --rt-steps, in Myr")
+    ap.add_argument("--rt-conv-frac", type=float, default=0.0,
+                    help="share of cells allowed to still move when a radiation step stops")
     ap.add_argument("--corr-study", action="store_true",
                     help="compare the overlap-correction modes on the Stromgren workload and exit")
     ap.add_argument("--tune", action="store_true",
@@ -429,7 +431,7 @@ def main():
     rt = None
     if "steps" in w.extra or args.rt_steps:  # radiation steps with the chemistry iteration
         rt = {path: run_rt(nrt, w, nrt.MIXED if path == "mixed" else nrt.FP64, args.capacity,
-                           args.rt_steps, args.rt_dt_myr)
+                           args.rt_steps, args.rt_dt_myr, args.rt_conv_frac)
               for path in res}
         for path, v in rt.items():
             log(f"[{path}] {v['ms_per_rt_step']:.2f} ms per RT step, iterations {v['iterations']}"

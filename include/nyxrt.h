@@ -165,12 +165,17 @@ nrt_status nrt_trace_step(nrt_ctx* ctx, double* gamma_out, nrt_budget* budget);
 /* One radiation step of length dt_s (Secs. "Time integration" and
    "Iterative nonlinear solve"): iterate { trace with a = (1 - x_avg) n_H;
    update x by the time-averaged solution of Eq. chem_ode with C_H = 0 and
-   recombination coefficient alpha = clumping * alpha_B } until the largest
-   change of x_avg is below tol or max_iter passes, then commit x(dt).
+   recombination coefficient alpha = clumping * alpha_B } until at most
+   conv_frac * n^3 cells changed x_avg by tol or more in the last pass
+   (conv_frac = 0: every cell changed by less than tol), or max_iter passes;
+   then commit x(dt).  The paper iterates "until convergence" without a
+   criterion; conv_frac > 0 lets a few front cells keep moving.
    gamma_out: device n^3 FP64 (Gamma of the last pass); budget: host (last
-   pass); iters: host, passes done.  The context's x is updated. */
-nrt_status nrt_rt_step(nrt_ctx* ctx, double dt_s, double alpha, double tol, int32_t max_iter,
-                       double* gamma_out, nrt_budget* budget, int32_t* iters);
+   pass); iters: host, passes done.  The context's x is updated.
+   NRT_ERR_ARG for dt_s <= 0, alpha < 0, tol < 0, conv_frac outside [0, 1]
+   or max_iter < 1. */
+nrt_status nrt_rt_step(nrt_ctx* ctx, double dt_s, double alpha, double tol, double conv_frac,
+                       int32_t max_iter, double* gamma_out, nrt_budget* budget, int32_t* iters);
 
 /* Test hook: march k injected rays that never split (desc->n_min_ray must be
    0): origin host k*3 (cell units, inside the box), dir host k*3 unit

@@ -67,7 +67,7 @@ def lib():
         L.orc_chem_update.argtypes = [C.c_int64, dp, dp, dp, C.c_double, C.c_double, dp, dp,
                                       dp]
         L.orc_rt_step.argtypes = [C.POINTER(Params), dp, dp, C.c_int64, dp, dp, C.c_double,
-                                  C.c_double, C.c_double, C.c_int, C.c_int, dp,
+                                  C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, dp,
                                   C.POINTER(Budget), C.POINTER(C.c_int)]
         _lib = L
     return _lib
@@ -220,8 +220,11 @@ def chem_update(gamma, n_H, x0, dt, alpha, x_avg_guess=None):
     return xn.reshape(shape), xa.reshape(shape)
 
 
-def rt_step(params, n_H, x, pos, ndot, dt, alpha, tol=1e-6, max_iter=200, nthreads=None):
-    """One radiation step.  Returns (x_new, gamma, budget, iterations)."""
+def rt_step(params, n_H, x, pos, ndot, dt, alpha, tol=1e-6, max_iter=200, nthreads=None,
+            conv_frac=0.0):
+    """One radiation step.  Returns (x_new, gamma, budget, iterations).  The
+    iteration stops once at most conv_frac of the cells moved their step
+    average by tol or more (0: none did)."""
     n = params.n
     n_H = _f64(n_H, (n, n, n))
     x = _f64(x, (n, n, n)).copy()
@@ -232,7 +235,8 @@ def rt_step(params, n_H, x, pos, ndot, dt, alpha, tol=1e-6, max_iter=200, nthrea
     it = C.c_int(0)
     nt = nthreads or max(1, min(16, os.cpu_count() or 1))
     rc = lib().orc_rt_step(C.byref(params), _d(n_H), _d(x), pos.shape[0], _d(pos), _d(ndot),
-                           float(dt), float(alpha), float(tol), int(max_iter), int(nt),
+                           float(dt), float(alpha), float(tol), float(conv_frac), int(max_iter),
+                           int(nt),
                            _d(gamma), C.byref(b), C.byref(it))
     if rc:
         raise ValueError(f"orc_rt_step failed ({rc})")

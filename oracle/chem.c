@@ -60,7 +60,8 @@ void orc_chem_update(int64_t ncell, const double* gamma, const double* n_H, cons
 
 int orc_rt_step(const orc_params* p, const double* n_H, double* x, int64_t m,
                 const double* pos, const double* ndot, double dt, double alpha, double tol,
-                int max_iter, int nthreads, double* gamma, orc_budget* b, int* iters) {
+                double conv_frac, int max_iter, int nthreads, double* gamma, orc_budget* b,
+                int* iters) {
   if (!p || p->n < 1 || !(dt > 0.0) || max_iter < 1) return 1;
   const int64_t n = p->n, ncell = n * n * n;
   double* xav = (double*)malloc((size_t)ncell * sizeof(double));
@@ -76,13 +77,11 @@ int orc_rt_step(const orc_params* p, const double* n_H, double* x, int64_t m,
     rc = orc_trace(p, n_H, xav, m, pos, ndot, nthreads, gamma, b);
     if (rc) goto out;
     orc_chem_update(ncell, gamma, n_H, x, dt, alpha, xav, xnew, xav2);
-    double delta = 0.0;
-    for (int64_t c = 0; c < ncell; ++c) {
-      const double dlt = fabs(xav2[c] - xav[c]);
-      if (dlt > delta) delta = dlt;
-    }
+    int64_t changed = 0; /* cells whose step average moved by tol or more */
+    for (int64_t c = 0; c < ncell; ++c)
+      if (fabs(xav2[c] - xav[c]) >= tol) ++changed;
     memcpy(xav, xav2, (size_t)ncell * sizeof(double));
-    if (delta < tol) break;
+    if ((double)changed <= conv_frac * (double)ncell) break;
   }
   if (it > max_iter) it = max_iter;
   memcpy(x, xnew, (size_t)ncell * sizeof(double));

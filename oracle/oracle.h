@@ -141,11 +141,13 @@ void orc_chem_update(int64_t ncell, const double* gamma, const double* n_H,
                      const double* x_avg_guess, double* x_new, double* x_avg);
 
 /* One radiation step: iterate { trace with a = (1 - x_avg) n_H ; chemistry }
-   until max|delta x_avg| < tol or max_iter; commit x <- x(dt).
+   until at most conv_frac * n^3 cells changed x_avg by tol or more in the
+   last iteration (conv_frac = 0: every cell changed by less than tol), or
+   max_iter iterations; commit x <- x(dt).
    x: in/out n^3.  gamma: out (last trace).  iters: out.  Returns 0 on success. */
 int orc_rt_step(const orc_params* p, const double* n_H, double* x,
                 int64_t m, const double* pos, const double* ndot,
-                double dt, double alpha, double tol, int max_iter,
+                double dt, double alpha, double tol, double conv_frac, int max_iter,
                 int nthreads, double* gamma, orc_budget* b, int* iters);
 
 #ifdef __cplusplus

@@ -88,7 +88,7 @@ def load():
         "nrt_get_sources": (st, [_P, _D, _D, _D]),
         "nrt_merge_sources": (st, [_P, C.POINTER(MergeParams), C.POINTER(C.c_int64)]),
         "nrt_trace_step": (st, [_P, _P, C.POINTER(Budget)]),
-        "nrt_rt_step": (st, [_P, C.c_double, C.c_double, C.c_double, C.c_int32, _P,
+        "nrt_rt_step": (st, [_P, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32, _P,
                              C.POINTER(Budget), C.POINTER(C.c_int32)]),
         "nrt_trace_rays_debug": (st, [_P, C.c_int64, _D, _D, C.POINTER(C.c_int32), _D, _P,
                                       C.POINTER(Budget)]),
@@ -225,12 +225,14 @@ class Context:
         _check(load().nrt_trace_step(self._ctx, gamma.data_ptr(), C.byref(b)), self._ctx)
         return gamma, b.as_dict()
 
-    def rt_step(self, dt_s, alpha, tol=1e-6, max_iter=200, gamma=None):
+    def rt_step(self, dt_s, alpha, tol=1e-6, max_iter=200, gamma=None, conv_frac=0.0):
+        """nrt_rt_step: one radiation step; returns (gamma, budget, passes)."""
         gamma = self._gamma(gamma)
         b = Budget()
         it = C.c_int32(0)
         _check(load().nrt_rt_step(self._ctx, float(dt_s), float(alpha), float(tol),
-                                  int(max_iter), gamma.data_ptr(), C.byref(b), C.byref(it)),
+                                  float(conv_frac), int(max_iter), gamma.data_ptr(), C.byref(b),
+                                  C.byref(it)),
                self._ctx)
         return gamma, b.as_dict(), it.value
 

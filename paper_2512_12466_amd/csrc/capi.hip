@@ -691,11 +691,11 @@ nrt_status nrt_healpix_dirs(nrt_ctx* c, int32_t level, int64_t first, int64_t co
   return NRT_OK;
 }
 
-nrt_status nrt_rt_step(nrt_ctx* c, double dt_s, double alpha, double tol, int32_t max_iter,
-                       double* gamma_out, nrt_budget* budget, int32_t* iters) {
+nrt_status nrt_rt_step(nrt_ctx* c, double dt_s, double alpha, double tol, double conv_frac,
+                       int32_t max_iter, double* gamma_out, nrt_budget* budget, int32_t* iters) {
   if (!c) return fail(nullptr, NRT_ERR_ARG, "ctx is NULL");
-  if (!(dt_s > 0.0) || !(alpha >= 0.0) || !(tol >= 0.0) || max_iter < 1 || !gamma_out ||
-      !budget)
+  if (!(dt_s > 0.0) || !(alpha >= 0.0) || !(tol >= 0.0) || !(conv_frac >= 0.0) ||
+      !(conv_frac <= 1.0) || max_iter < 1 || !gamma_out || !budget)
     return fail(c, NRT_ERR_ARG, "bad rt_step arguments");
   double* x_avg = reinterpret_cast<double*>(c->scratch);
   double* x_new = x_avg + c->lay.cells;
@@ -707,14 +707,13 @@ nrt_status nrt_rt_step(nrt_ctx* c, double dt_s, double alpha, double tol, int32_
     if (st) break;
     st = trace_pass(c, gamma_out, budget);
     if (st) break;
-    HIP_OR_FAIL(c, hipMemsetAsync(&c->acc->chem_delta_bits, 0, sizeof(unsigned long long),
+    HIP_OR_FAIL(c, hipMemsetAsync(&c->acc->chem_changed, 0, sizeof(unsigned long long),
                                   c->stream));
-    HIP_OR_FAIL(c, nrt::launch_chem(c, gamma_out, dt_s, alpha, x_avg, x_new));
+    HIP_OR_FAIL(c, nrt::launch_chem(c, gamma_out, dt_s, alpha, tol, x_avg, x_new));
     st = sync_read_accum(c);
     if (st) break;
-    double delta;
-    std::memcpy(&delta, &c->h_acc->chem_delta_bits, sizeof(delta));
-    if (delta < tol || it >= max_iter) break;
+    const double changed = double(c->h_acc->chem_changed);
+    if (changed <= conv_frac * double(c->lay.cells) || it >= max_iter) break;
   }
   if (st) {
     prep_absorber(c, c->x);

@@ -13,8 +13,9 @@ namespace nrt {
 namespace {
 
 __global__ void k_chem(const double* __restrict__ gamma, const double* __restrict__ n_H,
-                       const double* __restrict__ x0, double dt, double alpha, int64_t ncell,
-                       double* x_avg, double* x_new, unsigned long long* max_delta_bits) {
+                       const double* __restrict__ x0, double dt, double alpha, double tol,
+                       int64_t ncell, double* x_avg, double* x_new,
+                       unsigned long long* changed) {
   unsigned long long local = 0;
   for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < ncell;
        c += int64_t(gridDim.x) * blockDim.x) {
@@ -41,16 +42,10 @@ __global__ void k_chem(const double* __restrict__ gamma, const double* __restric
     }
     x_avg[c] = xav;
     x_new[c] = xend;
-    const double dlt = fabs(xav - guess);
-    const unsigned long long bits = static_cast<unsigned long long>(__double_as_longlong(dlt));
-    if (bits > local) local = bits;
+    if (fabs(xav - guess) >= tol) ++local;
   }
-  // non-negative doubles order like their bit patterns
-  for (int off = 32; off > 0; off >>= 1) {
-    const unsigned long long o = __shfl_xor(local, off);
-    if (o > local) local = o;
-  }
-  if (__lane_id() == 0 && local) atomicMax(max_delta_bits, local);
+  for (int off = 32; off > 0; off >>= 1) local += __shfl_xor(local, off);
+  if (__lane_id() == 0 && local) atomicAdd(changed, local);
 }
 
 __global__ void k_copy(const double* __restrict__ src, double* dst, int64_t count) {
@@ -61,13 +56,12 @@ __global__ void k_copy(const double* __restrict__ src, double* dst, int64_t coun
 
 }  // namespace
 
-hipError_t launch_chem(const nrt_ctx* c, const double* gamma, double dt, double alpha,
+hipError_t launch_chem(const nrt_ctx* c, const double* gamma, double dt, double alpha, double tol,
                        double* x_avg, double* x_new) {
   int64_t blocks = (c->lay.cells + 255) / 256;
   if (blocks > int64_t(c->cu_count) * 16) blocks = int64_t(c->cu_count) * 16;
   hipLaunchKernelGGL(k_chem, dim3(unsigned(blocks)), dim3(256), 0, c->stream, gamma, c->n_H,
-                     c->x, dt, alpha, c->lay.cells, x_avg, x_new,
-                     &c->acc->chem_delta_bits);
+                     c->x, dt, alpha, tol, c->lay.cells, x_avg, x_new, &c->acc->chem_changed);
   return hipGetLastError();
 }
 

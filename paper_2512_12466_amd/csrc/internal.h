@@ -35,7 +35,7 @@ struct Accum {
   unsigned long long invalid;  // input cells failing validation
   unsigned long long claim;  // rays claimed so far in the current march launch
   unsigned long long out_count[kMaxLevel + 2];  // rays pushed into each level queue
-  unsigned long long chem_delta_bits;  // max |dx_avg| as the bits of a non-negative double
+  unsigned long long chem_changed;  // cells whose x_avg moved by the tolerance or more
   unsigned long long claim_lv[kMaxLevel + 2];  // claim counters of a device-driven pass
 };
 
@@ -161,7 +161,7 @@ hipError_t run_merge(nrt_ctx* c, const nrt_merge_params& mp, const double* h_ndo
                      std::vector<double>& out6, std::string& why);
 
 // chem.hip
-hipError_t launch_chem(const nrt_ctx* c, const double* gamma, double dt, double alpha,
+hipError_t launch_chem(const nrt_ctx* c, const double* gamma, double dt, double alpha, double tol,
                        double* x_avg, double* x_new);
 hipError_t launch_copy(const nrt_ctx* c, const double* src, double* dst);
 

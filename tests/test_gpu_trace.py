@@ -138,6 +138,23 @@ def test_trace_fp64_matches_oracle(gpu, orc, periodic, corr):
     assert b["emitted"] == rb["emitted"]
 
 
+@pytest.mark.parametrize("n,periodic", [(13, True), (31, False), (33, True)])
+def test_odd_grids_match_oracle(gpu, orc, n, periodic):
+    """Grids whose cell count is not a multiple of the 8-cell Gamma line (the
+    last line of the LDS deposit table reaches past the grid): both paths
+    against the oracle."""
+    nH, x, pos, ndot, h = field_case(n, 300 + n, m=4)
+    kw = dict(periodic=periodic, n_min_ray=4.0, l_max=7, tau_max=25.0, n_th=4e-4)
+    ref, rb = orc.trace(orc.make_params(n, h, **kw), nH, x, pos, ndot)
+    got, b = run_gpu(gpu, n, h, nH, x, pos, ndot, 0, **kw)
+    assert rel_err(got, ref)[0] <= 1e-10
+    assert b["segments"] == rb["segments"] and b["splits"] == rb["splits"]
+    assert budget_err(b, rb) <= 1e-10
+    gm, bm = run_gpu(gpu, n, h, nH, x, pos, ndot, 1, **kw)
+    assert rel_err(gm, ref)[0] <= 1e-4
+    assert budget_err(bm, rb) <= 1e-6
+
+
 @pytest.mark.parametrize("periodic", [True, False])
 @pytest.mark.parametrize("corr", [2, 4])
 def test_trace_mixed_matches_oracle(gpu, orc, periodic, corr):
@@ -277,6 +294,35 @@ def test_rt_step_stromgren(gpu, orc):
         r_n = (3 * x_gpu.sum() / (4 * math.pi)) ** (1 / 3)
         r_a = r_s * (1 - math.exp(-step * dt / t_rec)) ** (1 / 3)
         assert r_n / r_a == pytest.approx(1.0, abs=0.02)
+    ctx.destroy()
+
+
+def test_rt_step_convergence_share(gpu, orc):
+    """Radiation steps that stop once at most 0.1 % of the cells still move
+    (conv_frac), on the GPU against the oracle with the same rule; invalid
+    shares are rejected."""
+    w = W.config1()
+    kw = dict(periodic=False, n_min_ray=w.n_min_ray, l_max=w.l_max, tau_max=w.tau_max,
+              n_th=w.n_th)
+    alpha = w.extra["alpha_B"] * w.extra["clumping"]
+    dt = w.extra["dt_s"]
+    p = orc.make_params(w.n, w.h_cm, **kw)
+    ctx = gpu.init_grid(gpu.make_desc(w.n, w.h_cm, **kw), w.n_H, w.x, device="cuda:0",
+                        max_sources=1, ray_capacity=1 << 18)
+    ctx.add_sources(w.pos, w.ndot)
+    for bad in (-0.1, 1.5):
+        with pytest.raises(gpu.NyxRTError):
+            ctx.rt_step(dt, alpha, conv_frac=bad)
+    x_ref = w.x.copy()
+    for step in range(3):
+        x_ref, _, _, it_ref = orc.rt_step(p, w.n_H, x_ref, w.pos, w.ndot, dt, alpha,
+                                          conv_frac=1e-3)
+        _, _, it = ctx.rt_step(dt, alpha, conv_frac=1e-3)
+        assert abs(it - it_ref) <= 1, (step, it, it_ref)
+        if it == it_ref:
+            assert np.abs(ctx.get_ionization().cpu().numpy() - x_ref).max() <= 1e-6
+        else:  # one pass apart near the threshold: keep the two in step
+            ctx.set_ionization(x_ref)
     ctx.destroy()
 
 

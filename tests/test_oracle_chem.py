@@ -103,3 +103,26 @@ def test_stromgren_test_a(orc):
         ion = ((x - x_old) * w.n_H).sum() * h ** 3
         rec = (xa * xa * w.n_H * w.n_H * a_eff).sum() * h ** 3 * dt
         assert (ion + rec) / (b["absorbed"] * dt) == pytest.approx(1.0, abs=2e-3)
+
+
+def test_rt_step_convergence_share(orc):
+    """The iteration stops once at most conv_frac of the cells moved their
+    step-averaged ionized fraction by tol or more: conv_frac = 1 stops after
+    the first pass, a looser share never needs more passes than conv_frac = 0
+    (every cell below tol), and conv_frac = 0 is the default rule."""
+    w = W.config1()
+    p = orc.make_params(w.n, w.h_cm, periodic=False, n_min_ray=w.n_min_ray, l_max=w.l_max,
+                        tau_max=w.tau_max, n_th=w.n_th)
+    a_eff = w.extra["alpha_B"] * w.extra["clumping"]
+    dt = w.extra["dt_s"]
+    args = (p, w.n_H, w.x, w.pos, w.ndot, dt, a_eff)
+    x_all, _, _, it_all = orc.rt_step(*args, tol=1e-6, max_iter=200, conv_frac=0.0)
+    x_def, _, _, it_def = orc.rt_step(*args, tol=1e-6, max_iter=200)
+    assert it_def == it_all and np.array_equal(x_def, x_all)
+    _, _, _, it_one = orc.rt_step(*args, tol=1e-6, max_iter=200, conv_frac=1.0)
+    assert it_one == 1
+    x_loose, _, _, it_loose = orc.rt_step(*args, tol=1e-6, max_iter=200, conv_frac=1e-3)
+    assert 1 <= it_loose <= it_all
+    # the looser rule stops early only while few cells still move: the step's
+    # end state differs little
+    assert np.abs(x_loose - x_all).max() < 0.05
