@@ -14,13 +14,15 @@ import numpy as np
 from . import build as _build
 
 CORR_NONE, CORR_LINEAR, CORR_CONSERVATIVE, CORR_SQUARED, CORR_NAIVE = range(5)
+SPEC_MONO, SPEC_BLACKBODY, SPEC_POWERLAW = range(3)
 MAX_LEVEL = 24
 
 
 class Params(C.Structure):
     _fields_ = [("n", C.c_int32), ("h_cm", C.c_double), ("periodic", C.c_int32),
                 ("sigma0", C.c_double), ("n_min_ray", C.c_double), ("l_max", C.c_int32),
-                ("tau_max", C.c_double), ("n_th", C.c_double), ("corr", C.c_int32)]
+                ("tau_max", C.c_double), ("n_th", C.c_double), ("corr", C.c_int32),
+                ("spectrum", C.c_int32), ("spec_param", C.c_double)]
 
 
 class Budget(C.Structure):
@@ -57,6 +59,7 @@ def lib():
                                 C.POINTER(Budget)]
         L.orc_trace_rays.argtypes = [C.POINTER(Params), dp, dp, C.c_int64, dp, dp, ip, dp,
                                      dp, C.POINTER(Budget), C.c_int64, lp, dp, lp, lp]
+        L.orc_spectrum_eval.argtypes = [C.c_int32, C.c_double, C.c_int64, dp, dp, dp, dp, dp]
         L.orc_dedupe_sort.argtypes = [C.c_int32, C.c_int64, dp, dp, ip, dp]
         L.orc_dedupe_sort.restype = C.c_int64
         L.orc_max_radius.argtypes = [C.POINTER(MergeParams), C.c_int32, C.c_int32, dp,
@@ -93,9 +96,23 @@ def _f64(a, shape=None):
 
 
 def make_params(n, h_cm, periodic=False, sigma0=6.30e-18, n_min_ray=4.0, l_max=10,
-                tau_max=30.0, n_th=0.0, corr=CORR_CONSERVATIVE):
+                tau_max=30.0, n_th=0.0, corr=CORR_CONSERVATIVE, spectrum=SPEC_MONO,
+                spec_param=0.0):
     return Params(int(n), float(h_cm), int(bool(periodic)), float(sigma0), float(n_min_ray),
-                  int(l_max), float(tau_max), float(n_th), int(corr))
+                  int(l_max), float(tau_max), float(n_th), int(corr), int(spectrum),
+                  float(spec_param))
+
+
+def spectrum_eval(kind, param, tau, dtau=None):
+    """Frequency integrals of Eq. lut_eqn per unit photon rate at threshold
+    optical depths tau (cell depths dtau): returns (F, D, G) arrays."""
+    tau = _f64(tau).reshape(-1)
+    dt = np.zeros_like(tau) if dtau is None else _f64(np.broadcast_to(dtau, tau.shape))
+    F, D, G = np.zeros_like(tau), np.zeros_like(tau), np.zeros_like(tau)
+    if lib().orc_spectrum_eval(int(kind), float(param), tau.size, _d(tau), _d(dt), _d(F),
+                               _d(D), _d(G)):
+        raise ValueError(f"bad spectrum ({kind}, {param})")
+    return F, D, G
 
 
 def pix2vec_nest(level, pix):

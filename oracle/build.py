@@ -8,7 +8,7 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["healpix.c", "trace.c", "merge.c", "chem.c"]
+SOURCES = ["healpix.c", "spectrum.c", "trace.c", "merge.c", "chem.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

@@ -16,7 +16,8 @@
  *   orc_pix2vec_nest  HEALPix nested pixel centres (Gorski et al. 2005, the
  *                     pixelisation cited in Sec. "Adaptive ray tracing").
  *   orc_trace         Alg. trace_rays with the functors of Alg. functors,
- *                     flux from Eq. lut_eqn (monochromatic, V_box = h^3),
+ *                     flux from Eq. lut_eqn (V_box = h^3; monochromatic, or
+ *                     integrated over a photon spectrum in spectrum.c),
  *                     optical depth from Eq. optical_depth with a_abs, split
  *                     test Eq. split_criterion, overlap correction
  *                     Eqs. correction / secondary_correction / new_correction /
@@ -24,6 +25,8 @@
  *   orc_trace_rays    the same march for injected rays with no splitting.
  *   orc_dedupe_sort, orc_max_radius, orc_merge_sources
  *                     Sec. "Source Merging Algorithm" and Alg. source_merge.
+ *   orc_spectrum_eval the frequency integrals of Eq. lut_eqn against the
+ *                     threshold optical depth (Sec. "Flux computation").
  *   orc_chem_update, orc_rt_step
  *                     Eq. chem_ode with the time-averaged integration of
  *                     C2-Ray (Sec. "Time integration") and the fixed-point
@@ -51,6 +54,16 @@ enum {
                                 dropped when n'_H < n_th ("naive thresholding")  */
 };
 
+/* source spectra (Sec. "Flux computation"); the cross-section is
+   sigma_nu = sigma0 (nu / nu_0)^-3 */
+enum {
+  ORC_SPEC_MONO = 0,      /* all photons at the threshold nu_0                 */
+  ORC_SPEC_BLACKBODY = 1, /* photon spectrum ~ nu^2 / (e^{h nu / k T} - 1),
+                             param = T [K] in [1e3, 1e7], h nu_0 = 13.6 eV     */
+  ORC_SPEC_POWERLAW = 2   /* photon spectrum ~ nu^-alpha, param = alpha in
+                             [2.5, 50]                                         */
+};
+
 typedef struct {
   int32_t n;          /* cells per side                                   */
   double h_cm;        /* cell width in cm                                 */
@@ -61,6 +74,8 @@ typedef struct {
   double tau_max;     /* optical-depth cap                                */
   double n_th;        /* neighbour density threshold, cm^-3               */
   int32_t corr;       /* ORC_CORR_*                                       */
+  int32_t spectrum;   /* ORC_SPEC_*; tau and tau_max are at the threshold  */
+  double spec_param;  /* temperature or power-law index (see ORC_SPEC_*)  */
 } orc_params;
 
 #define ORC_MAX_LEVEL 24
@@ -99,6 +114,14 @@ int orc_trace_rays(const orc_params* p, const double* n_H, const double* x,
                    double* gamma, orc_budget* b,
                    int64_t max_log, int64_t* log_cell, double* log_ds,
                    int64_t* log_ijk, int64_t* n_log);
+
+/* Frequency integrals of Eq. lut_eqn per unit photon rate, at threshold
+   optical depths tau[i] (and cell depths dtau[i], may be NULL = 0):
+   F = photons left, D = photons a cell absorbs, G = the thin-cell limit
+   D / dtau as dtau -> 0.  Any output may be NULL.  Returns nonzero on a bad
+   spectrum. */
+int orc_spectrum_eval(int32_t kind, double param, int64_t k, const double* tau,
+                      const double* dtau, double* F, double* D, double* G);
 
 /* ---------------- source merging ---------------- */
 typedef struct {

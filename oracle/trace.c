@@ -9,11 +9,14 @@
  *   raymarch   Alg. functors: march cell by cell with the Amanatides-Woo
  *              traversal while the ray does not need to split, is inside the
  *              domain and has travelled less than sqrt(3) L_box.
- *   flux       Eq. lut_eqn for a monochromatic source at threshold with
- *              V_shell replaced by V_box = h^3 (footnote to Alg. functors):
+ *   flux       Eq. lut_eqn with V_shell replaced by V_box = h^3 (footnote
+ *              to Alg. functors).  Monochromatic at threshold:
  *              Gamma = L e^{-tau} (1 - e^{-dtau}) / (n_HI h^3), and its
  *              n_HI -> 0 limit L e^{-tau} sigma0 dl / h^3 (footnote in
  *              Sec. "Numerical instability for low n_H neighbor cells").
+ *              With a spectrum (spectrum.c), tau is the threshold optical
+ *              depth and Gamma = L D(tau, dtau) / (n_HI h^3), with the limit
+ *              L G(tau) sigma0 dl / h^3; a ray carries L F(tau) photons.
  *   depth      Eq. optical_depth with the absorber a_abs = (1 - x) n_H of
  *              Sec. "Geometric correction" (reading: the printed integrand
  *              "sigma x n_HI" is garbled; a_abs is used).
@@ -61,6 +64,7 @@
 #include <string.h>
 
 #include "oracle.h"
+#include "spectrum.h"
 
 typedef struct {
   int level;
@@ -89,6 +93,7 @@ typedef struct {
   const orc_params* p;
   const double* n_H;
   const double* a; /* absorber (1 - x) n_H */
+  orc_spectrum spec;
   double s_max;
   double h3;
   double r2split[ORC_MAX_LEVEL + 1];
@@ -119,7 +124,13 @@ static double plane_t(double o, double d, int64_t i) {
   return INFINITY;
 }
 
-static void grid_setup(orc_grid* g, const orc_params* p, const double* n_H, const double* a) {
+/* photons per unit L left after threshold optical depth tau */
+static double transmitted(const orc_grid* g, double tau) {
+  return g->p->spectrum == ORC_SPEC_MONO ? exp(-tau) : orc_spectrum_F(&g->spec, tau);
+}
+
+static int grid_setup(orc_grid* g, const orc_params* p, const double* n_H, const double* a) {
+  if (orc_spectrum_init(&g->spec, p->spectrum, p->spec_param)) return 1;
   g->p = p;
   g->n_H = n_H;
   g->a = a;
@@ -131,6 +142,7 @@ static void grid_setup(orc_grid* g, const orc_params* p, const double* n_H, cons
     g->sqrt_omega[l] = sqrt(omega);
     g->r2split[l] = p->n_min_ray > 0.0 ? 1.0 / (p->n_min_ray * omega) : INFINITY;
   }
+  return 0;
 }
 
 /* One cell segment [s, t_next] of a ray in unwrapped cell i: Eq. lut_eqn,
@@ -145,13 +157,22 @@ static double segment(const orc_grid* g, const double o[3], const double d[3], i
   const double a_c = g->a[c];
   const double dl = ds * p->h_cm;               /* path length in cm       */
   const double dtau = p->sigma0 * a_c * dl;      /* Eq. optical_depth       */
-  const double P = L * exp(-tau);                /* photons/s entering      */
-  const double dN = P * (-expm1(-dtau));         /* photons/s absorbed      */
   double G;                                      /* Eq. lut_eqn, V = h^3    */
-  if (a_c > 0.0)
-    G = dN / (a_c * g->h3);
-  else
-    G = P * p->sigma0 * dl / g->h3;
+  double dN;                                     /* photons/s absorbed      */
+  if (p->spectrum == ORC_SPEC_MONO) {
+    const double P = L * exp(-tau);              /* photons/s entering      */
+    dN = P * (-expm1(-dtau));
+    if (a_c > 0.0)
+      G = dN / (a_c * g->h3);
+    else
+      G = P * p->sigma0 * dl / g->h3;
+  } else {
+    dN = L * orc_spectrum_D(&g->spec, tau, dtau);
+    if (a_c > 0.0)
+      G = dN / (a_c * g->h3);
+    else
+      G = L * orc_spectrum_G(&g->spec, tau) * p->sigma0 * dl / g->h3;
+  }
   b->absorbed += dN;
 
   double fc = 1.0;
@@ -245,21 +266,21 @@ static int march(const orc_grid* g, const double o[3], const double d[3], orc_ra
   }
   double s = r.s, tau = r.tau;
   if (!p->periodic && !inside(i, n)) {
-    b->escaped += r.L * exp(-tau);
+    b->escaped += r.L * transmitted(g, tau);
     return 0;
   }
   for (;;) {
     if (p->periodic && s >= g->s_max) {
-      b->escaped += r.L * exp(-tau);
+      b->escaped += r.L * transmitted(g, tau);
       return 0;
     }
     if (tau >= p->tau_max) {
-      b->truncated += r.L * exp(-tau);
+      b->truncated += r.L * transmitted(g, tau);
       return 0;
     }
     if (can_split && s * s > g->r2split[r.level]) {
       if (r.level >= p->l_max) {
-        b->truncated += r.L * exp(-tau);
+        b->truncated += r.L * transmitted(g, tau);
         return 0;
       }
       b->splits += 1;
@@ -289,7 +310,7 @@ static int march(const orc_grid* g, const double o[3], const double d[3], orc_ra
     t[ax] = plane_t(o[ax], d[ax], i[ax]);
     b->segments += 1;
     if (!p->periodic && !inside(i, n)) {
-      b->escaped += r.L * exp(-tau);
+      b->escaped += r.L * transmitted(g, tau);
       return 0;
     }
   }
@@ -300,6 +321,7 @@ static int check_params(const orc_params* p) {
   if (p->l_max < 0 || p->l_max >= ORC_MAX_LEVEL) return 1;
   if (!(p->tau_max > 0.0) || !(p->n_min_ray >= 0.0)) return 1;
   if (p->corr < ORC_CORR_NONE || p->corr > ORC_CORR_NAIVE) return 1;
+  if (p->spectrum < ORC_SPEC_MONO || p->spectrum > ORC_SPEC_POWERLAW) return 1;
   return 0;
 }
 
@@ -380,7 +402,10 @@ int orc_trace(const orc_params* p, const double* n_H, const double* x, int64_t m
   double* a = make_absorber(ncell, n_H, x);
   if (!a) return 2;
   orc_grid g;
-  grid_setup(&g, p, n_H, a);
+  if (grid_setup(&g, p, n_H, a)) {
+    free(a);
+    return 1;
+  }
 
   /* private FP64 Gamma per thread, capped at ~16 GB in total */
   int64_t nt = nthreads < 1 ? 1 : nthreads;
@@ -417,6 +442,7 @@ int orc_trace(const orc_params* p, const double* n_H, const double* x, int64_t m
   free(w);
   free(th);
   free(a);
+  orc_spectrum_free(&g.spec);
   pthread_mutex_destroy(&lock);
   return err ? 2 : 0;
 }
@@ -434,7 +460,10 @@ int orc_trace_rays(const orc_params* p, const double* n_H, const double* x, int6
   double* a = make_absorber(ncell, n_H, x);
   if (!a) return 2;
   orc_grid g;
-  grid_setup(&g, p, n_H, a);
+  if (grid_setup(&g, p, n_H, a)) {
+    free(a);
+    return 1;
+  }
   orc_log lg = {max_log, 0, log_cell, log_ds, log_ijk};
   for (int64_t r = 0; r < k; ++r) {
     b->emitted += L[r];
@@ -445,5 +474,6 @@ int orc_trace_rays(const orc_params* p, const double* n_H, const double* x, int6
   }
   if (n_log) *n_log = lg.n_log;
   free(a);
+  orc_spectrum_free(&g.spec);
   return 0;
 }
