@@ -63,6 +63,24 @@ typedef enum {
                                 where n'_H < n_th ("naive thresholding")           */
 } nrt_corr;
 
+/* Source spectrum (Sec. "Flux computation").  The photo-ionisation
+   cross-section falls as sigma0 (nu/nu_0)^-3 above the threshold nu_0
+   (h nu_0 = 13.6 eV).  For a polychromatic spectrum a ray's optical depth tau
+   is the one at the threshold, and the flux of Eq. lut_eqn integrated over
+   frequency is evaluated from a table in tau built at nrt_init_grid: the
+   share F(tau) of a ray's photons left after tau, and its thin-cell slope
+   -F'(tau) for cells with no absorber (the optically thin table of the
+   footnote in Sec. "Numerical instability for low n_H neighbor cells").  The
+   cap tau_max then applies to the whole spectrum: a ray stops once
+   F(tau) <= e^{-tau_max}, the share a monochromatic ray keeps at tau_max. */
+typedef enum {
+  NRT_SPEC_MONO = 0,      /* every photon at nu_0 (spec_param ignored)           */
+  NRT_SPEC_BLACKBODY = 1, /* photon rate per frequency ~ nu^2 / (e^{h nu/kT} - 1);
+                             spec_param = T [K] in [1e3, 1e7]                      */
+  NRT_SPEC_POWERLAW = 2   /* photon rate per frequency ~ nu^-alpha;
+                             spec_param = alpha in [2.5, 50]                       */
+} nrt_spectrum;
+
 #define NRT_MAX_LEVEL 14 /* HEALPix level cap: 12 * 4^14 pixels fit in 32 bits */
 
 typedef struct {
@@ -77,6 +95,8 @@ typedef struct {
   double n_th;        /* neighbour density threshold [cm^-3] (Eq. new_correction) */
   int32_t corr;       /* nrt_corr                                                 */
   int32_t precision;  /* nrt_precision                                            */
+  int32_t spectrum;   /* nrt_spectrum (0 = monochromatic)                         */
+  double spec_param;  /* temperature or power-law index, see nrt_spectrum        */
 } nrt_grid_desc;
 
 /* Source-merging parameters (Sec. "Source Merging Algorithm"). */
@@ -115,7 +135,9 @@ nrt_status nrt_workspace_bytes(const nrt_grid_desc* desc, int64_t max_sources,
    else NRT_ERR_ARG).  workspace: device, ws_bytes >= nrt_workspace_bytes(),
    256-byte aligned, owned by the caller and used until nrt_destroy.
    hip_stream: a hipStream_t (NULL = the null stream).  *out receives the
-   context; nothing is created on failure. */
+   context; nothing is created on failure.  A polychromatic spectrum is
+   tabulated here: NRT_ERR_ARG if its transmitted share F does not fall to
+   1e-6 e^{-tau_max} within tau < 2^64 (spectra too hard for the table). */
 nrt_status nrt_init_grid(nrt_ctx** out, const nrt_grid_desc* desc, const double* n_H,
                          const double* x_ion, int64_t max_sources, int64_t ray_capacity,
                          void* workspace, size_t ws_bytes, void* hip_stream);

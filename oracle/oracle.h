@@ -71,10 +71,11 @@ typedef struct {
   double sigma0;      /* photo-ionisation cross-section at threshold, cm^2 */
   double n_min_ray;   /* N_min^ray of Eq. split_criterion; 0 = never split */
   int32_t l_max;      /* HEALPix level cap                                */
-  double tau_max;     /* optical-depth cap                                */
+  double tau_max;     /* optical-depth cap; with a spectrum the ray stops
+                         once F(tau) <= e^{-tau_max}                      */
   double n_th;        /* neighbour density threshold, cm^-3               */
   int32_t corr;       /* ORC_CORR_*                                       */
-  int32_t spectrum;   /* ORC_SPEC_*; tau and tau_max are at the threshold  */
+  int32_t spectrum;   /* ORC_SPEC_*; a ray's tau is at the threshold      */
   double spec_param;  /* temperature or power-law index (see ORC_SPEC_*)  */
 } orc_params;
 

@@ -24,7 +24,13 @@
  *              new_secondary (the paper's final "conservative
  *              thresholding" is ORC_CORR_CONSERVATIVE).
  *   ray_fltr   terminate on tau >= tau_max, on level l_max needing a split,
- *              and on s >= sqrt(3) L_box in the periodic case.
+ *              and on s >= sqrt(3) L_box in the periodic case.  With a
+ *              spectrum the optical-depth cap applies to the whole spectrum:
+ *              the ray stops once the share of its photons left, F(tau),
+ *              is at most e^{-tau_max}, the share a monochromatic ray keeps
+ *              at tau_max (reading: the paper caps the optical depth of a
+ *              monochromatic ray; at the threshold a hard spectrum would
+ *              still carry a sizeable share of its photons there).
  *   s_copy /   4 children at level l+1, pixel 4 pix + k, same s and tau,
  *   s_tsfm     L / 4, restarting at o + s d_child (Alg. functors).
  *
@@ -94,6 +100,7 @@ typedef struct {
   const double* n_H;
   const double* a; /* absorber (1 - x) n_H */
   orc_spectrum spec;
+  double t_min; /* e^{-tau_max} */
   double s_max;
   double h3;
   double r2split[ORC_MAX_LEVEL + 1];
@@ -135,6 +142,7 @@ static int grid_setup(orc_grid* g, const orc_params* p, const double* n_H, const
   g->n_H = n_H;
   g->a = a;
   g->s_max = p->periodic ? sqrt(3.0) * (double)p->n : INFINITY;
+  g->t_min = exp(-p->tau_max);
   g->h3 = p->h_cm * p->h_cm * p->h_cm;
   for (int l = 0; l <= ORC_MAX_LEVEL; ++l) {
     /* Omega(l) = 4 pi / (12 * 4^l), Eq. split_criterion */
@@ -274,7 +282,7 @@ static int march(const orc_grid* g, const double o[3], const double d[3], orc_ra
       b->escaped += r.L * transmitted(g, tau);
       return 0;
     }
-    if (tau >= p->tau_max) {
+    if (p->spectrum == ORC_SPEC_MONO ? tau >= p->tau_max : transmitted(g, tau) <= g->t_min) {
       b->truncated += r.L * transmitted(g, tau);
       return 0;
     }

@@ -17,6 +17,7 @@ MAX_LEVEL = 14
 
 FP64, MIXED = 0, 1
 CORR_NONE, CORR_LINEAR, CORR_CONSERVATIVE, CORR_SQUARED, CORR_NAIVE = range(5)
+SPEC_MONO, SPEC_BLACKBODY, SPEC_POWERLAW = range(3)
 STATUS = {0: "NRT_OK", 1: "NRT_ERR_ARG", 2: "NRT_ERR_STATE", 3: "NRT_ERR_NOMEM",
           4: "NRT_ERR_OVERFLOW", 5: "NRT_ERR_DEVICE", 6: "NRT_ERR_INTERNAL"}
 
@@ -31,7 +32,7 @@ class GridDesc(C.Structure):
     _fields_ = [("n", C.c_int32), ("h_cm", C.c_double), ("periodic", C.c_int32),
                 ("sigma0", C.c_double), ("n_min_ray", C.c_double), ("l_max", C.c_int32),
                 ("tau_max", C.c_double), ("n_th", C.c_double), ("corr", C.c_int32),
-                ("precision", C.c_int32)]
+                ("precision", C.c_int32), ("spectrum", C.c_int32), ("spec_param", C.c_double)]
 
 
 class MergeParams(C.Structure):
@@ -125,9 +126,11 @@ def _dp(a):
 
 
 def make_desc(n, h_cm, periodic=False, sigma0=6.30e-18, n_min_ray=4.0, l_max=10, tau_max=30.0,
-              n_th=0.0, corr=CORR_CONSERVATIVE, precision=FP64):
+              n_th=0.0, corr=CORR_CONSERVATIVE, precision=FP64, spectrum=SPEC_MONO,
+              spec_param=0.0):
     return GridDesc(int(n), float(h_cm), int(bool(periodic)), float(sigma0), float(n_min_ray),
-                    int(l_max), float(tau_max), float(n_th), int(corr), int(precision))
+                    int(l_max), float(tau_max), float(n_th), int(corr), int(precision),
+                    int(spectrum), float(spec_param))
 
 
 def make_merge_params(dr=2.0, x_th=0.9, f_req=0.9, n_min=8, r_max=8.0, f_ov=1.0, eps=1e-6,

@@ -50,6 +50,15 @@ bool check_desc(const nrt_grid_desc* d, std::string& why) {
   if (d->corr < NRT_CORR_NONE || d->corr > NRT_CORR_NAIVE) return why = "bad corr", false;
   if (d->precision != NRT_FP64 && d->precision != NRT_MIXED) return why = "bad precision", false;
   if (d->periodic != 0 && d->periodic != 1) return why = "periodic must be 0 or 1", false;
+  if (d->spectrum == NRT_SPEC_BLACKBODY) {
+    if (!(d->spec_param >= 1e3 && d->spec_param <= 1e7))
+      return why = "blackbody temperature must be in [1e3, 1e7] K", false;
+  } else if (d->spectrum == NRT_SPEC_POWERLAW) {
+    if (!(d->spec_param >= 2.5 && d->spec_param <= 50.0))
+      return why = "power-law index must be in [2.5, 50]", false;
+  } else if (d->spectrum != NRT_SPEC_MONO) {
+    return why = "bad spectrum", false;
+  }
   return true;
 }
 
@@ -115,6 +124,9 @@ MarchArgs base_args(const nrt_ctx* c, double* gamma) {
   a.src_l0 = c->src_l0;
   a.dirs = c->dirs;
   a.dir_max_level = c->lay.dir_levels;
+  a.spec_nint = c->spec_nint;
+  a.spec64 = c->spec64;
+  a.spec32 = c->spec32;
   for (int l = 0; l <= nrt::kMaxLevel; ++l) a.sqrt_omega_tab[l] = c->sqrt_omega[l];
   a.acc = c->acc;
   a.lds_keys_fit = ((int64_t(d.n) * d.n * d.n) >> 3 < (int64_t(1) << 32) - 1) ? 1 : 0;
@@ -412,6 +424,11 @@ Layout plan_layout(const nrt_grid_desc& d, int64_t max_sources, int64_t capacity
   L.dir_levels = std::min(d.l_max, nrt::kDirTableMaxLevel);
   L.dirs = off;
   off = align256(off + size_t(nrt::dir_table_offset(L.dir_levels + 1)) * 24);
+  L.spec = off;
+  if (d.spectrum != NRT_SPEC_MONO)  // node moments, then the FP64 and FP32 records
+    off = align256(off + size_t(3 * kSpecNodes) * 8) +
+          size_t(kSpecNodes - 1) * (sizeof(SpecRec64) + sizeof(SpecRec32));
+  off = align256(off);
   L.scratch = off;
   // x_avg and x_new of the chemistry; also staging for injected rays and
   // direction queries, hence a 4 MiB floor
@@ -494,6 +511,11 @@ nrt_status nrt_init_grid(nrt_ctx** out, const nrt_grid_desc* desc, const double*
   c->src_pos = reinterpret_cast<double*>(c->ws + L.srcpos);
   c->src_l0 = reinterpret_cast<double*>(c->ws + L.srcl0);
   c->dirs = reinterpret_cast<double*>(c->ws + L.dirs);
+  if (desc->spectrum != NRT_SPEC_MONO) {
+    c->spec_nodes = reinterpret_cast<double*>(c->ws + L.spec);
+    c->spec64 = reinterpret_cast<nrt::SpecRec64*>(c->ws + align256(L.spec + 3 * nrt::kSpecNodes * 8));
+    c->spec32 = reinterpret_cast<nrt::SpecRec32*>(c->spec64 + (nrt::kSpecNodes - 1));
+  }
   char* q = c->ws + L.queues;
   const size_t cap = size_t(L.capacity);
   for (int l = 0; l <= nrt::kMaxLevel; ++l) c->queue[l] = RayQueue{nullptr, nullptr, nullptr, nullptr};
@@ -528,6 +550,10 @@ nrt_status nrt_init_grid(nrt_ctx** out, const nrt_grid_desc* desc, const double*
     e = nrt::launch_healpix(l, 0, 12 * (int64_t(1) << (2 * l)), c->dirs + 3 * nrt::dir_table_offset(l),
                             c->stream);
   if (e != hipSuccess) return bail(hip_fail(c, e, "direction table"));
+  if (desc->spectrum != NRT_SPEC_MONO) {
+    st = nrt::build_spectrum_table(c);
+    if (st) return bail(st);
+  }
   *out = c;
   return NRT_OK;
 }

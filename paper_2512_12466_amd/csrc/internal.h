@@ -19,12 +19,36 @@ constexpr int kBlock = 256;  // threads per block of the march kernels (4 waves)
 // One ray in a level queue (structure of arrays, 24 bytes per ray).  The
 // HEALPix level is the queue's, the rate follows from the source and level,
 // and the direction from (level, pix).  w is the optical depth tau (FP64
-// path) or the transmitted fraction exp(-tau) (mixed path).
+// path) or the transmitted fraction exp(-tau) (mixed path); with a
+// polychromatic source it is the threshold optical depth in both paths.
 struct RayQueue {
   uint32_t* src;
   uint32_t* pix;
   double* s;
   double* w;
+};
+
+// Polychromatic sources (Sec. "Flux computation"): Phi(tau) = -ln F(tau),
+// F the share of a ray's photons left after threshold optical depth tau, is
+// tabulated on the octaves [2^e, 2^(e+1)) of 1 + tau, each cut into
+// kSpecSub equal intervals, for e < kSpecMaxOctaves.  Interval q = e kSpecSub
+// + m covers 1 + tau in 2^e [1 + m/kSpecSub, 1 + (m+1)/kSpecSub); its local
+// coordinate x in [0, 1) and index follow from the bits of 1 + tau, and
+// Phi = c0 + c1 x + ... + c5 x^5 there (quintic Hermite through Phi, Phi'
+// and Phi'' at both ends).
+constexpr int kSpecLog2Sub = 6;
+constexpr int kSpecSub = 1 << kSpecLog2Sub;
+constexpr int kSpecMaxOctaves = 64;
+constexpr int kSpecNodes = kSpecMaxOctaves * kSpecSub + 1;
+
+// FP64 record of an interval: c1..c5, c0, padding (64 B)
+struct SpecRec64 {
+  double c[8];
+};
+// mixed-path record: c1..c5 in FP32, c0 in FP64 (32 B)
+struct SpecRec32 {
+  float c[6];
+  double c0;
 };
 
 // Device accumulators of one pass.
@@ -50,8 +74,11 @@ struct MarchArgs {
   double h_cm, sigma0, tau_max, s_max, h3;
   double r2split;    // split iff s*s > r2split (this level)
   double sqrt_omega; // sqrt of the pixel solid angle (this level)
-  double t_min;      // exp(-tau_max): mixed-path termination threshold
+  double t_min;      // exp(-tau_max): mixed-path and polychromatic termination threshold
   float kf;          // (float)(sigma0 * h_cm)
+  int32_t spec_nint;            // polychromatic: table intervals in use
+  const SpecRec64* spec64;      // polychromatic table (FP64 path, and ray set-up)
+  const SpecRec32* spec32;      // the same for the mixed path
   const double* a64; // absorber, sign bit set = not a usable neighbour
   const float* a32;
   double* gamma;
@@ -91,7 +118,7 @@ __host__ __device__ inline int64_t dir_table_offset(int level) {
 }
 
 struct Layout {
-  size_t n_H, x, a, srcpos, srcl0, srcaux, queues, accum, dirs, scratch, total;
+  size_t n_H, x, a, srcpos, srcl0, srcaux, queues, accum, dirs, spec, scratch, total;
   int64_t cells, max_sources, capacity;
   int levels;      // number of level queues (levels 1..l_max)
   int dir_levels;  // direction table covers levels 0..dir_levels
@@ -124,6 +151,10 @@ struct nrt_ctx {
   double* a64;
   float* a32;
   double* dirs;
+  nrt::SpecRec64* spec64;
+  nrt::SpecRec32* spec32;
+  double* spec_nodes;  // m0, mean, variance at the table's nodes
+  int32_t spec_nint;
   double* src_pos;
   double* src_l0;
   nrt::RayQueue queue[nrt::kMaxLevel + 1];
@@ -159,6 +190,11 @@ hipError_t launch_healpix(int level, int64_t first, int64_t count, double* out, 
 size_t merge_bytes_per_source();
 hipError_t run_merge(nrt_ctx* c, const nrt_merge_params& mp, const double* h_ndot, int64_t m,
                      std::vector<double>& out6, std::string& why);
+
+// spectrum.hip: the polychromatic table.  Fills c->spec64 / c->spec32 and
+// c->spec_nint; returns NRT_ERR_ARG (with c->err set) for a spectrum whose
+// transmitted share does not fall to 1e-6 e^{-tau_max} within the table.
+nrt_status build_spectrum_table(nrt_ctx* c);
 
 // chem.hip
 hipError_t launch_chem(const nrt_ctx* c, const double* gamma, double dt, double alpha, double tol,

@@ -213,9 +213,107 @@ struct RayState {
   uint32_t src, pix;
 };
 
+// ---- polychromatic sources: Phi(tau) = -ln F(tau) from the table ----
+struct SpecPos {
+  int q;         // interval
+  double x;      // local coordinate in [0, 1)
+  double inv_w;  // 1 / interval width in tau (a power of two)
+};
+
+// interval and local coordinate of tau >= 0, exactly, from the bits of 1 + tau
+__device__ __forceinline__ SpecPos spec_pos(double tau) {
+  constexpr int kShift = 52 - kSpecLog2Sub;
+  const double v = 1.0 + tau;
+  const uint64_t b = uint64_t(__double_as_longlong(v));
+  const int e = int(b >> 52) - 1023;
+  SpecPos p;
+  p.q = (e << kSpecLog2Sub) + int((b >> kShift) & uint64_t(kSpecSub - 1));
+  p.inv_w = __longlong_as_double((long long)(1023 + kSpecLog2Sub - e) << 52);
+  p.x = (v - __longlong_as_double((long long)(b & ~((uint64_t(1) << kShift) - 1)))) * p.inv_w;
+  return p;
+}
+
+// (p(x2) - p(x1)) / (x2 - x1) for p = c0 + c1 x + ... + c5 x^5, as
+// sum_k c_k h_{k-1}(x1, x2) with h_j the complete homogeneous polynomial of
+// degree j; free of cancellation, and p'(x1) when x2 = x1
+template <typename T>
+__device__ __forceinline__ T spec_slope(const T* c, T x1, T x2) {
+  const T h1 = x1 + x2;
+  const T x1s = x1 * x1;
+  const T h2 = fma(x2, h1, x1s);
+  const T x1c = x1s * x1;
+  const T h3 = fma(x2, h2, x1c);
+  const T h4 = fma(x2, h3, x1c * x1);
+  return fma(c[4], h4, fma(c[3], h3, fma(c[2], h2, fma(c[1], h1, c[0]))));
+}
+
+// c1..c5 of interval q in the path's precision
+template <bool MIXED, typename Args, typename V>
+__device__ __forceinline__ void spec_coef(Args& A, int q, V* c) {
+  if constexpr (MIXED) {
+    const float4 lo = *reinterpret_cast<const float4*>(A.spec32[q].c);
+    c[0] = lo.x;
+    c[1] = lo.y;
+    c[2] = lo.z;
+    c[3] = lo.w;
+    c[4] = A.spec32[q].c[4];
+  } else {
+    const double2* r = reinterpret_cast<const double2*>(A.spec64[q].c);
+    const double2 a = r[0], b = r[1];
+    c[0] = a.x;
+    c[1] = a.y;
+    c[2] = b.x;
+    c[3] = b.y;
+    c[4] = A.spec64[q].c[4];
+  }
+}
+
+template <bool MIXED, typename Args>
+__device__ __forceinline__ double spec_c0(Args& A, int q) {
+  return MIXED ? A.spec32[q].c0 : A.spec64[q].c[5];
+}
+
+// Phi(tau) in FP64 (ray set-up); +inf past the table
+template <typename Args>
+__device__ double spec_phi(Args& A, double tau) {
+  const SpecPos p = spec_pos(tau);
+  if (p.q >= A.spec_nint) return __builtin_inf();
+  double c[5];
+  spec_coef<false>(A, p.q, c);
+  return A.spec64[p.q].c[5] + p.x * spec_slope(c, 0.0, p.x);
+}
+
+// Rise of Phi over [tau, tau + dtau]: the optical depth that attenuates the
+// whole spectrum across the cell, so that the cell absorbs the share
+// 1 - e^{-rise} of the photons the ray carries.  `slope` receives the mean
+// dPhi/dtau over the cell when the cell lies within one interval, which is
+// dPhi/dtau at tau when dtau = 0 (the thin-cell limit).  Past the table's end
+// the rise is infinite: the cell absorbs everything the ray still carries.
+template <bool MIXED, typename Args, typename V>
+__device__ __forceinline__ V spec_rise(Args& A, double tau, V dtau, V& slope) {
+  const SpecPos p1 = spec_pos(tau);
+  const SpecPos p2 = spec_pos(tau + double(dtau));
+  V c[5];
+  spec_coef<MIXED>(A, p1.q, c);
+  if (p2.q == p1.q) {
+    const V sl = spec_slope(c, V(p1.x), V(p2.x));
+    slope = sl * V(p1.inv_w);
+    return (dtau * V(p1.inv_w)) * sl;
+  }
+  slope = V(0);
+  if (p2.q >= A.spec_nint) return V(__builtin_inf());
+  // rest of the first interval, whole intervals between, start of the last
+  const V first = (V(1) - V(p1.x)) * spec_slope(c, V(p1.x), V(1));
+  spec_coef<MIXED>(A, p2.q, c);
+  const V last = V(p2.x) * spec_slope(c, V(0), V(p2.x));
+  const double mid = spec_c0<MIXED>(A, p2.q) - spec_c0<MIXED>(A, p1.q + 1);
+  return (first + last) + V(mid);
+}
+
 // One ray of a launch as queued: source, HEALPix pixel, path length and
 // carried weight (optical depth in the FP64 path, transmitted fraction in the
-// mixed one).  For injected rays `src` holds the ray's index.
+// mixed one, the threshold optical depth for a polychromatic source).  For
+// injected rays `src` holds the ray's index.
 struct Entry {
   uint32_t src, pix;
   double s, w;
@@ -223,14 +321,14 @@ struct Entry {
 
 // Entry r of the launch: a virtual spawn index, a queue slot or an injected
 // ray's index.
-template <bool MIXED, typename Args>
+template <bool W_IS_T, typename Args>
 __device__ __forceinline__ Entry load_entry(Args& A, int64_t r) {
   Entry e;
   if (A.level < 0) {
     e.src = uint32_t(r);
     e.pix = 0;
     e.s = 0.0;
-    e.w = MIXED ? 1.0 : 0.0;
+    e.w = W_IS_T ? 1.0 : 0.0;
   } else if (A.spawn) {
     if (r < (int64_t(1) << 32)) {
       const uint32_t r32 = uint32_t(r);
@@ -241,7 +339,7 @@ __device__ __forceinline__ Entry load_entry(Args& A, int64_t r) {
       e.pix = uint32_t(r % 12);
     }
     e.s = 0.0;
-    e.w = MIXED ? 1.0 : 0.0;
+    e.w = W_IS_T ? 1.0 : 0.0;
   } else {
     e.src = A.in.src[r];
     e.pix = A.in.pix[r];
@@ -253,7 +351,7 @@ __device__ __forceinline__ Entry load_entry(Args& A, int64_t r) {
 
 // Start the ray of entry e: direction, start cell and first absorber.
 // Returns kEscaped if it starts outside an open box, else kGoOn.
-template <bool MIXED, bool PERIODIC, typename Args>
+template <bool MIXED, bool PERIODIC, bool POLY, typename Args>
 __device__ int ray_init(RayState& R, Args& A, const Entry& e) {
   double w = e.w;
   if (A.level < 0) {  // injected rays: never split
@@ -299,7 +397,17 @@ __device__ int ray_init(RayState& R, Args& A, const Entry& e) {
   R.t0 = plane_t(R.o0, R.d0, R.i0);
   R.t1 = plane_t(R.o1, R.d1, R.i1);
   R.t2 = plane_t(R.o2, R.d2, R.i2);
-  if (MIXED) {
+  if constexpr (POLY) {
+    R.tau = w;
+    const double T = exp(-spec_phi(A, w));
+    if (MIXED) {
+      R.T = T;
+      R.absf = 0.0;
+      R.s_rate = float(R.L / A.h3);
+    } else {
+      R.P = R.L * T;
+    }
+  } else if (MIXED) {
     R.T = w;
     R.absf = 0.0;
     R.s_rate = float(R.L / A.h3);
@@ -328,13 +436,18 @@ __device__ int ray_init(RayState& R, Args& A, const Entry& e) {
 // slots taken by this call's deposits.  Memory latency is hidden by order:
 // the cell's absorber was loaded at the end of the previous step, and the
 // neighbour's is requested before the attenuation arithmetic that follows.
-template <bool MIXED, int CORR, bool PERIODIC, typename V>
+template <bool MIXED, int CORR, bool PERIODIC, bool POLY, typename V>
 __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab, LaneAcc& acc,
                         int& inserted) {
   const int n = A.n;
   constexpr bool open_box = !PERIODIC;
   if (PERIODIC && R.s >= A.s_max) return kEscaped;
-  if (MIXED ? (R.T <= A.t_min) : (R.tau >= A.tau_max)) return kTruncated;
+  // the optical-depth cap; for a spectrum, on the share of photons left
+  if constexpr (POLY) {
+    if (MIXED ? (R.T <= A.t_min) : (R.P <= R.L * A.t_min)) return kTruncated;
+  } else {
+    if (MIXED ? (R.T <= A.t_min) : (R.tau >= A.tau_max)) return kTruncated;
+  }
   if (R.s * R.s > R.r2s) return R.level >= A.l_max ? kTruncated : kSplit;
   // next crossing: lowest axis wins exact ties
   int ax = 0;
@@ -418,7 +531,13 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab
   if (MIXED) {
     a32 = fabsf(R.a32);
     const float dsf = float(ds);
-    const float dtau = A.kf * a32 * dsf;
+    float dtau = A.kf * a32 * dsf;
+    float slope32 = 1.0f;
+    if constexpr (POLY) {  // the whole spectrum's attenuation across the cell
+      const float dtau0 = dtau;
+      dtau = spec_rise<true>(A, R.tau, dtau0, slope32);
+      R.tau += double(dtau0);
+    }
     // surviving share e = exp(-dtau) from the hardware base-2 exponential
     // (1 ulp); absorbed share em = 1 - e, which for dtau < 1/8 comes from
     // its series (relative truncation error below dtau^5/720 < 5e-8) since
@@ -442,13 +561,15 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab
     R.T = Tn;
     R.absf += dT;
     G32 = a32 > 0.0f ? (R.s_rate * float(dT)) * __builtin_amdgcn_rcpf(a32)
-                     : R.s_rate * Tf * (A.kf * dsf);
+                     : R.s_rate * Tf * (A.kf * dsf) * slope32;
   } else {
     a64 = fabs(R.a64);
     const double dl = ds * A.h_cm;
     const double dtau = A.sigma0 * a64 * dl;
-    const double dN = R.P * (-expm1(-dtau));
-    G64 = a64 > 0.0 ? dN / (a64 * A.h3) : R.P * A.sigma0 * dl / A.h3;
+    double rise = dtau, slope64 = 1.0;
+    if constexpr (POLY) rise = spec_rise<false>(A, R.tau, dtau, slope64);
+    const double dN = R.P * (-expm1(-rise));
+    G64 = a64 > 0.0 ? dN / (a64 * A.h3) : R.P * A.sigma0 * dl * slope64 / A.h3;
     acc.absorbed += dN;
     R.P -= dN;
     R.tau += dtau;
@@ -564,7 +685,7 @@ __device__ __forceinline__ void push_pending(unsigned long long* count, const Ra
 // children's start state in registers; the wavefront appends the children of
 // all pending splits to the next level's queue with one atomicAdd once 32 are
 // pending (or a pending lane splits again, or the run ends).
-template <bool MIXED, int CORR, bool PERIODIC>
+template <bool MIXED, int CORR, bool PERIODIC, bool POLY>
 __global__ __launch_bounds__(kBlock) void k_march(MarchArgs A) {
   using V = typename std::conditional<MIXED, float, double>::type;
   // per-wavefront deposit tables, reused for the budget reduction at the end
@@ -616,8 +737,8 @@ __global__ __launch_bounds__(kBlock) void k_march(MarchArgs A) {
         const int64_t avail = pool_end - pool;
         const unsigned rank = lanes_below(idle);
         if (!busy && int64_t(rank) < avail) {
-          const Entry e = load_entry<MIXED>(F, F.begin + pool + rank);
-          const int start = ray_init<MIXED, PERIODIC>(R, F, e);
+          const Entry e = load_entry<MIXED && !POLY>(F, F.begin + pool + rank);
+          const int start = ray_init<MIXED, PERIODIC, POLY>(R, F, e);
           busy = start == kGoOn;
           if (!busy) acc.escaped += MIXED ? R.L * R.T : R.P;
         }
@@ -630,7 +751,7 @@ __global__ __launch_bounds__(kBlock) void k_march(MarchArgs A) {
     }
     int code = kGoOn, inserted = 0;
     if (busy) {
-      code = ray_step<MIXED, CORR, PERIODIC>(R, A, tab, acc, inserted);
+      code = ray_step<MIXED, CORR, PERIODIC, POLY>(R, A, tab, acc, inserted);
       if (code != kGoOn) {
         busy = false;
         const double carried = MIXED ? R.L * R.T : R.P;
@@ -653,7 +774,7 @@ __global__ __launch_bounds__(kBlock) void k_march(MarchArgs A) {
       p_src = R.src;
       p_pix = R.pix;
       p_s = R.s;
-      p_w = MIXED ? R.T : R.tau;
+      p_w = (MIXED && !POLY) ? R.T : R.tau;
     }
     if (__popcll(__ballot(pend)) >= 32) {
       ArgsK& F = fresh_args();
@@ -775,22 +896,29 @@ namespace {
 // the march instantiation for a precision, correction mode and boundary
 using MarchKernel = void (*)(MarchArgs);
 
-template <bool MIXED, bool PERIODIC>
+template <bool MIXED, bool PERIODIC, bool POLY>
 MarchKernel march_for_corr(int corr) {
   switch (corr) {
-    case NRT_CORR_NONE: return k_march<MIXED, NRT_CORR_NONE, PERIODIC>;
-    case NRT_CORR_LINEAR: return k_march<MIXED, NRT_CORR_LINEAR, PERIODIC>;
-    case NRT_CORR_SQUARED: return k_march<MIXED, NRT_CORR_SQUARED, PERIODIC>;
-    case NRT_CORR_NAIVE: return k_march<MIXED, NRT_CORR_NAIVE, PERIODIC>;
-    default: return k_march<MIXED, NRT_CORR_CONSERVATIVE, PERIODIC>;
+    case NRT_CORR_NONE: return k_march<MIXED, NRT_CORR_NONE, PERIODIC, POLY>;
+    case NRT_CORR_LINEAR: return k_march<MIXED, NRT_CORR_LINEAR, PERIODIC, POLY>;
+    case NRT_CORR_SQUARED: return k_march<MIXED, NRT_CORR_SQUARED, PERIODIC, POLY>;
+    case NRT_CORR_NAIVE: return k_march<MIXED, NRT_CORR_NAIVE, PERIODIC, POLY>;
+    default: return k_march<MIXED, NRT_CORR_CONSERVATIVE, PERIODIC, POLY>;
   }
 }
 
+template <bool POLY>
+MarchKernel march_for_spectrum(const nrt_grid_desc& d) {
+  if (d.precision == NRT_MIXED)
+    return d.periodic ? march_for_corr<true, true, POLY>(d.corr)
+                      : march_for_corr<true, false, POLY>(d.corr);
+  return d.periodic ? march_for_corr<false, true, POLY>(d.corr)
+                    : march_for_corr<false, false, POLY>(d.corr);
+}
+
 MarchKernel march_kernel(const nrt_grid_desc& d) {
-  const bool mixed = d.precision == NRT_MIXED;
-  if (mixed)
-    return d.periodic ? march_for_corr<true, true>(d.corr) : march_for_corr<true, false>(d.corr);
-  return d.periodic ? march_for_corr<false, true>(d.corr) : march_for_corr<false, false>(d.corr);
+  return d.spectrum != NRT_SPEC_MONO ? march_for_spectrum<true>(d)
+                                     : march_for_spectrum<false>(d);
 }
 
 }  // namespace

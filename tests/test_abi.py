@@ -49,13 +49,22 @@ def test_status_strings_and_workspace_plan():
     d11, d12 = nrt.make_desc(32, 1e20, l_max=11), nrt.make_desc(32, 1e20, l_max=12)
     assert (nrt.workspace_bytes(d12, 100, 1 << 16) - nrt.workspace_bytes(d11, 100, 1 << 16)
             == 24 * (1 << 16))
+    # polychromatic table: node moments (3 x 4097 FP64, padded to 256 B) and
+    # 4096 interval records of 64 B (FP64) + 32 B (FP32), padded to 256 B
+    dp = nrt.make_desc(32, 1e20, l_max=7, spectrum=nrt.SPEC_BLACKBODY, spec_param=5e4)
+    nodes = (3 * 4097 * 8 + 255) // 256 * 256
+    assert nrt.workspace_bytes(dp, 100, 1 << 16) - b64 == nodes + 4096 * 96
 
 
 @pytest.mark.parametrize("field,value", [("n", 0), ("h_cm", -1.0), ("l_max", 15),
                                          ("tau_max", 0.0), ("corr", 9), ("precision", 2),
-                                         ("n_min_ray", -1.0), ("periodic", 3)])
+                                         ("n_min_ray", -1.0), ("periodic", 3),
+                                         ("spectrum", 3), ("spec_param", 1e8),
+                                         ("spec_param", 0.0)])
 def test_bad_descriptor_rejected(field, value):
     d = nrt.make_desc(16, 1e20)
+    if field == "spec_param":  # a blackbody out of [1e3, 1e7] K
+        d.spectrum = nrt.SPEC_BLACKBODY
     setattr(d, field, value)
     with pytest.raises(nrt.NyxRTError) as e:
         nrt.workspace_bytes(d, 10, 1 << 16)

@@ -15,7 +15,8 @@ fixes them independently of the oracle's quadrature:
   * D / dtau -> G, telescoping sums of D, convexity of ln F;
   * in a trace: a fully ionized grid deposits G(0) times the monochromatic
     Gamma; a single ray deposits L D(tau_in, dtau) per cell (alpha = 4 closed
-    form on the brute-force geometry); photons are conserved.
+    form on the brute-force geometry) and stops at the first cell boundary
+    where F <= e^{-tau_max}; photons are conserved.
 """
 import math
 
@@ -159,7 +160,7 @@ def test_trace_conserves_photons(orc, kind, param):
     x = np.where(g.random((n, n, n)) < 0.3, 1.0, 0.0)
     pos = W.uniform_positions(4, n, g)
     ndot = W.lognormal_values(4, 1e50, 1.0, g)
-    p = orc.make_params(n, h, periodic=True, n_min_ray=4.0, l_max=6, tau_max=30.0,
+    p = orc.make_params(n, h, periodic=True, n_min_ray=4.0, l_max=6, tau_max=3.0,
                         n_th=1e-5, spectrum=kind, spec_param=param)
     gamma, b = orc.trace(p, nH, x, pos, ndot)
     assert b["splits"] > 0 and b["truncated"] > 0
@@ -168,3 +169,23 @@ def test_trace_conserves_photons(orc, kind, param):
     # conservative correction: every absorbed photon is in Gamma a h^3
     a = (1 - x) * nH
     assert np.sum(gamma * a * h ** 3) == pytest.approx(b["absorbed"], rel=1e-11)
+
+
+def test_stop_when_photon_share_reaches_cap(orc):
+    """alpha = 4 along an axis through a uniform medium of dtau = 0.5 per cell:
+    the ray stops at the first boundary k with F(k/2) <= e^{-tau_max}, carrying
+    L F(k/2) into the truncated term (a monochromatic ray would stop at
+    k = 2 tau_max)."""
+    n, h = 64, 1.0e20
+    a = 0.5 / (SIG * h)
+    nH, x = np.full((n, n, n), a), np.zeros((n, n, n))
+    L = 1e48
+    for tau_max in (1.0, 2.0, 2.7):
+        p = orc.make_params(n, h, periodic=False, n_min_ray=0.0, corr=orc.CORR_NONE,
+                            tau_max=tau_max, spectrum=orc.SPEC_POWERLAW, spec_param=4.0)
+        gamma, b, _ = orc.trace_rays(p, nH, x, np.array([[0.0, 32.5, 32.5]]),
+                                     np.array([[1.0, 0.0, 0.0]]), 0, L)
+        k = next(k for k in range(1, n) if _f_pl4(0.5 * k) <= math.exp(-tau_max))
+        assert b["segments"] == k and k > 2 * tau_max
+        assert b["truncated"] == pytest.approx(L * _f_pl4(0.5 * k), rel=1e-12)
+        assert b["absorbed"] == pytest.approx(L * (1 - _f_pl4(0.5 * k)), rel=1e-12)
