@@ -52,19 +52,39 @@ def make_workload(name):
     return w
 
 
+def parse_spectrum(text):
+    """'mono', 'bb:<T in K>' (blackbody) or 'pl:<alpha>' (power law) -> (kind, param)."""
+    if text in ("", "mono"):
+        return 0, 0.0
+    kind, _, param = text.partition(":")
+    kinds = {"bb": 1, "pl": 2}
+    if kind not in kinds or not param:
+        raise SystemExit(f"bad --spectrum {text!r}: mono, bb:<T> or pl:<alpha>")
+    return kinds[kind], float(param)
+
+
+def spectrum_config(spec):
+    kind, param = spec
+    return ("mono" if kind == 0 else
+            {"kind": "blackbody" if kind == 1 else "power-law",
+             "T_K" if kind == 1 else "alpha": param})
+
+
 def subset_indices(m, k, seed=11):
     import numpy as np
     g = np.random.default_rng(12466 + 950 + seed)
     return np.sort(g.choice(m, size=k, replace=False))
 
 
-def run_path(nrt, w, precision, steps, warmup, capacity, graph=0, sources=0, tune=False):
+def run_path(nrt, w, precision, steps, warmup, capacity, graph=0, sources=0, tune=False,
+             spectrum=(0, 0.0)):
     """Time `steps` trace passes (after `warmup` untimed ones) of one
     arithmetic path.  Merging workloads merge first (timed on its own); with
     `sources`, a seeded subset of the (merged) catalogue is traced."""
     import torch
     desc = nrt.make_desc(w.n, w.h_cm, periodic=w.periodic, n_min_ray=w.n_min_ray, l_max=w.l_max,
-                         tau_max=w.tau_max, n_th=w.n_th, precision=precision)
+                         tau_max=w.tau_max, n_th=w.n_th, precision=precision,
+                         spectrum=spectrum[0], spec_param=spectrum[1])
     ctx = nrt.init_grid(desc, w.n_H, w.x, device="cuda:0", max_sources=len(w.ndot),
                         ray_capacity=capacity)
     ctx.add_sources(w.pos, w.ndot)
@@ -114,7 +134,7 @@ def run_path(nrt, w, precision, steps, warmup, capacity, graph=0, sources=0, tun
                 merge_ms=merge_ms, sources_traced=m_traced, tuning=tuning)
 
 
-def run_rt(nrt, w, precision, capacity, steps=0, dt_myr=0.0, conv_frac=0.0):
+def run_rt(nrt, w, precision, capacity, steps=0, dt_myr=0.0, conv_frac=0.0, spectrum=(0, 0.0)):
     """Radiation steps: each iterates trace passes and the chemistry update to
     convergence (nrt_rt_step).  The Stromgren workload uses its own step
     count and Delta t and reports the final ionized radius against the closed
@@ -128,7 +148,8 @@ def run_rt(nrt, w, precision, capacity, steps=0, dt_myr=0.0, conv_frac=0.0):
     dt = w.extra["dt_s"] if stromgren else dt_myr * W.MYR_S
     nsteps = w.extra["steps"] if stromgren else steps
     desc = nrt.make_desc(w.n, w.h_cm, periodic=w.periodic, n_min_ray=w.n_min_ray, l_max=w.l_max,
-                         tau_max=w.tau_max, n_th=w.n_th, precision=precision)
+                         tau_max=w.tau_max, n_th=w.n_th, precision=precision,
+                         spectrum=spectrum[0], spec_param=spectrum[1])
     ctx = nrt.init_grid(desc, w.n_H, w.x, device="cuda:0", max_sources=len(w.ndot),
                         ray_capacity=capacity)
     ctx.add_sources(w.pos, w.ndot)
@@ -335,12 +356,13 @@ def summarize_counters(d, out):
     print("\n".join(lines))
 
 
-def cpu_baseline(w, sources, threads):
+def cpu_baseline(w, sources, threads, spectrum=(0, 0.0)):
     import oracle
     import workloads as W
     s = W.subset(w, sources)
     p = oracle.make_params(w.n, w.h_cm, periodic=w.periodic, n_min_ray=w.n_min_ray,
-                           l_max=w.l_max, tau_max=w.tau_max, n_th=w.n_th)
+                           l_max=w.l_max, tau_max=w.tau_max, n_th=w.n_th,
+                           spectrum=spectrum[0], spec_param=spectrum[1])
     t0 = time.perf_counter()
     _, b = oracle.trace(p, s.n_H, s.x, s.pos, s.ndot, nthreads=threads)
     dt = time.perf_counter() - t0
@@ -377,6 +399,9 @@ def main():
                     help="share of cells allowed to still move when a radiation step stops")
     ap.add_argument("--corr-study", action="store_true",
                     help="compare the overlap-correction modes on the Stromgren workload and exit")
+    ap.add_argument("--spectrum", default="mono",
+                    help="source spectrum: mono (13.6 eV), bb:<T> (blackbody at T kelvin) or "
+                         "pl:<alpha> (power law)")
     ap.add_argument("--tune", action="store_true",
                     help="pick launch parameters with nrt_autotune before timing")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -403,6 +428,7 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: 3 x {args.calibrate_copy} MiB")
         del src, dst
+    spectrum = parse_spectrum(args.spectrum)
     w = make_workload(args.workload)
     if args.corr_study:
         if "steps" not in w.extra:
@@ -416,7 +442,7 @@ def main():
     for path in args.paths.split(","):
         prec = nrt.MIXED if path == "mixed" else nrt.FP64
         r = run_path(nrt, w, prec, args.steps, args.warmup, args.capacity, args.graph,
-                     args.sources, args.tune)
+                     args.sources, args.tune, spectrum)
         r["segments_per_s_kernel"] = r["segments_per_step"] * args.steps / (
             r["kernel_ms_total"] / 1e3)
         res[path] = r
@@ -431,14 +457,16 @@ def main():
     rt = None
     if "steps" in w.extra or args.rt_steps:  # radiation steps with the chemistry iteration
         rt = {path: run_rt(nrt, w, nrt.MIXED if path == "mixed" else nrt.FP64, args.capacity,
-                           args.rt_steps, args.rt_dt_myr, args.rt_conv_frac)
+                           args.rt_steps, args.rt_dt_myr, args.rt_conv_frac, spectrum)
               for path in res}
         for path, v in rt.items():
             log(f"[{path}] {v['ms_per_rt_step']:.2f} ms per RT step, iterations {v['iterations']}"
                 + (f", r/r_closed-form {v['r_ratio']:.4f}" if "r_ratio" in v else ""))
     head = "mixed" if "mixed" in res else next(iter(res))
     h = res[head]
-    counters = read_counters()
+    # the committed counter summary covers the default workload's monochromatic pass
+    counters = (read_counters() if args.workload == "lognormal-128-64src" and spectrum[0] == 0
+                and not args.sources else None)
     out = {
         "metric": METRIC, "value": round(h["segments_per_s"], 1), "unit": "ray-segments/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -448,7 +476,7 @@ def main():
         "config": {"workload": w.name, "n": w.n, "sources": int(len(w.ndot)),
                    "periodic": bool(w.periodic), "n_min_ray": w.n_min_ray, "l_max": w.l_max,
                    "tau_max": w.tau_max, "path": head, "decisions": "f64",
-                   "graph": bool(h["graph"])},
+                   "graph": bool(h["graph"]), "spectrum": spectrum_config(spectrum)},
         "roofline": roofline(head, h, counters),
     }
     out["config"]["per_pass"] = {k: h["budget"][k] for k in ("segments", "rays", "splits")}
@@ -470,7 +498,7 @@ def main():
                                "roofline": roofline(path, r, counters)}
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sources, threads)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sources, threads, spectrum)
     print(json.dumps(out), flush=True)
 
 

@@ -685,8 +685,12 @@ __device__ __forceinline__ void push_pending(unsigned long long* count, const Ra
 // children's start state in registers; the wavefront appends the children of
 // all pending splits to the next level's queue with one atomicAdd once 32 are
 // pending (or a pending lane splits again, or the run ends).
+// The mixed polychromatic march is held to 128 VGPRs (it fits with no
+// spills), which keeps 4 waves per SIMD as its LDS allows; every other
+// instantiation is left to the compiler.
 template <bool MIXED, int CORR, bool PERIODIC, bool POLY>
-__global__ __launch_bounds__(kBlock) void k_march(MarchArgs A) {
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu((MIXED && POLY) ? 4 : 1, 8))) void k_march(MarchArgs A) {
   using V = typename std::conditional<MIXED, float, double>::type;
   // per-wavefront deposit tables, reused for the budget reduction at the end
   using Tab = LineTable<V>;
