@@ -335,7 +335,7 @@ def summarize_counters(d, out):
     lines = ["# HBM traffic of k_march from FETCH_SIZE / WRITE_SIZE counter runs",
              "# command (FETCH_SIZE; then WRITE_SIZE with -o write > write_bench.json): "
              "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o fetch -- "
-             "python3 bench.py --steps 1 --warmup 1 --no-cpu-baseline --calibrate-copy 1024 "
+             "python3 bench.py --steps 1 --warmup 2 --no-cpu-baseline --calibrate-copy 1024 "
              "> <dir>/fetch_bench.json",
              "# summarized with: python bench.py --summarize-counters <dir>",
              "# bytes per launch: counter KiB x 1024 / copy factor, averaged over the march "
