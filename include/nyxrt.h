@@ -184,6 +184,28 @@ nrt_status nrt_merge_sources(nrt_ctx* ctx, const nrt_merge_params* mp, int64_t* 
    cannot hold a split (Gamma then unspecified). */
 nrt_status nrt_trace_step(nrt_ctx* ctx, double* gamma_out, nrt_budget* budget);
 
+/* The same pass without a host round trip, for callers that record it in
+   their own hipGraph (stream capture on ctx's stream) or overlap it with
+   other work.  It enqueues the device-driven pass, one march launch per
+   HEALPix level with each level's ray count read from device memory, and
+   a kernel that writes the budget into device memory, then returns without
+   synchronising.  It allocates nothing, issues no memset or copy, and
+   clears its device state with kernels, so it may be called while ctx's
+   stream is being captured; a recorded pass replays with the source table,
+   gamma_out, budget_dev and dropped_dev it was recorded with, and with the
+   absorber field current at replay.
+   gamma_out: device n^3 FP64, overwritten.  budget_dev: device nrt_budget,
+   written by the pass.  dropped_dev: device uint64 or NULL, written with the
+   number of rays whose children did not fit their level's queue.  This form
+   cannot fall back to the host-driven chunked pass: when *dropped_dev is
+   nonzero, Gamma and the budget are incomplete; give ray_capacity at least
+   the widest level's ray count (budget.rays_per_level of nrt_trace_step).
+   NRT_ERR_STATE if the source table changed since the last pass and ctx's
+   stream is capturing (the table is copied from host memory then; run one
+   pass outside capture first).  Nothing is enqueued when a check fails. */
+nrt_status nrt_trace_step_async(nrt_ctx* ctx, double* gamma_out, nrt_budget* budget_dev,
+                                uint64_t* dropped_dev);
+
 /* One radiation step of length dt_s (Secs. "Time integration" and
    "Iterative nonlinear solve"): iterate { trace with a = (1 - x_avg) n_H;
    update x by the time-averaged solution of Eq. chem_ode with C_H = 0 and

@@ -89,6 +89,7 @@ def load():
         "nrt_get_sources": (st, [_P, _D, _D, _D]),
         "nrt_merge_sources": (st, [_P, C.POINTER(MergeParams), C.POINTER(C.c_int64)]),
         "nrt_trace_step": (st, [_P, _P, C.POINTER(Budget)]),
+        "nrt_trace_step_async": (st, [_P, _P, _P, _P]),
         "nrt_rt_step": (st, [_P, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32, _P,
                              C.POINTER(Budget), C.POINTER(C.c_int32)]),
         "nrt_trace_rays_debug": (st, [_P, C.c_int64, _D, _D, C.POINTER(C.c_int32), _D, _P,
@@ -137,6 +138,12 @@ def make_merge_params(dr=2.0, x_th=0.9, f_req=0.9, n_min=8, r_max=8.0, f_ov=1.0,
                       shell_level=3):
     return MergeParams(float(dr), float(x_th), float(f_req), int(n_min), float(r_max),
                        float(f_ov), float(eps), int(shell_level))
+
+
+def budget_from_device(t):
+    """The nrt_budget a device tensor holds (written by trace_step_async), as a dict."""
+    raw = bytes(t.detach().cpu().contiguous().view(-1).numpy().view(np.uint8)[:C.sizeof(Budget)])
+    return Budget.from_buffer_copy(raw).as_dict()
 
 
 def workspace_bytes(desc, max_sources, ray_capacity):
@@ -227,6 +234,26 @@ class Context:
         b = Budget()
         _check(load().nrt_trace_step(self._ctx, gamma.data_ptr(), C.byref(b)), self._ctx)
         return gamma, b.as_dict()
+
+    def trace_step_async(self, gamma=None, budget=None, dropped=None):
+        """nrt_trace_step_async: enqueue one pass on the context's stream and
+        return at once (capture-safe).  budget / dropped: device tensors of
+        sizeof(nrt_budget) bytes / one int64, allocated when None.  Returns
+        (gamma, budget, dropped); decode the budget with budget_from_device()
+        once the stream has finished."""
+        import torch
+        gamma = self._gamma(gamma)
+        # empty, not zeros: a fill on torch's stream could land after the pass,
+        # which writes every byte of both
+        if budget is None:
+            budget = torch.empty(C.sizeof(Budget), dtype=torch.uint8, device=self.device)
+        if dropped is None:
+            dropped = torch.empty(1, dtype=torch.int64, device=self.device)
+        assert budget.numel() * budget.element_size() >= C.sizeof(Budget)
+        assert budget.device == self.device and dropped.device == self.device
+        _check(load().nrt_trace_step_async(self._ctx, gamma.data_ptr(), budget.data_ptr(),
+                                           dropped.data_ptr()), self._ctx)
+        return gamma, budget, dropped
 
     def rt_step(self, dt_s, alpha, tol=1e-6, max_iter=200, gamma=None, conv_frac=0.0):
         """nrt_rt_step: one radiation step; returns (gamma, budget, passes)."""

@@ -635,6 +635,31 @@ nrt_status nrt_trace_step(nrt_ctx* c, double* gamma_out, nrt_budget* budget) {
   return trace_pass(c, gamma_out, budget);
 }
 
+nrt_status nrt_trace_step_async(nrt_ctx* c, double* gamma_out, nrt_budget* budget_dev,
+                                uint64_t* dropped_dev) {
+  if (!c) return fail(nullptr, NRT_ERR_ARG, "ctx is NULL");
+  if (!gamma_out || !budget_dev) return fail(c, NRT_ERR_ARG, "NULL gamma_out or budget_dev");
+  if (c->sources_dirty) {  // the table upload copies from host memory and synchronises
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_OR_FAIL(c, hipStreamIsCapturing(c->stream, &cs));
+    if (cs != hipStreamCaptureStatusNone)
+      return fail(c, NRT_ERR_STATE,
+                  "the source table changed since the last pass: run one pass outside stream "
+                  "capture first");
+    const nrt_status st = upload_sources(c);
+    if (st) return st;
+  }
+  double emitted = 0.0;
+  for (double v : c->h_ndot) emitted += v;
+  HIP_OR_FAIL(c, enqueue_device_pass(c, c->stream, gamma_out));
+  HIP_OR_FAIL(c, nrt::launch_budget(c->acc, budget_dev, dropped_dev, emitted,
+                                    12 * int64_t(c->h_ndot.size()), c->desc.l_max, c->stream));
+  c->last_pass_graph = 0;
+  c->launches = 0;  // not timed
+  c->march_ms = 0.0;
+  return NRT_OK;
+}
+
 nrt_status nrt_trace_rays_debug(nrt_ctx* c, int64_t k, const double* origin, const double* dir,
                                 const int32_t* level, const double* L, double* gamma_out,
                                 nrt_budget* budget) {

@@ -185,6 +185,10 @@ hipError_t launch_zero_accum(Accum* acc, hipStream_t s);
 hipError_t launch_march(const nrt_ctx* c, const MarchArgs& a, int64_t rays, hipStream_t st);
 hipError_t march_blocks_per_cu(const nrt_grid_desc& d, int* blocks);
 hipError_t launch_healpix(int level, int64_t first, int64_t count, double* out, hipStream_t s);
+// budget of a device-driven pass into device memory: emitted and the spawn
+// count come from the host, the rest from the accumulator block
+hipError_t launch_budget(const Accum* acc, nrt_budget* out, uint64_t* dropped, double emitted,
+                         int64_t spawned, int l_max, hipStream_t s);
 
 // merge.hip
 size_t merge_bytes_per_source();

@@ -866,6 +866,27 @@ __global__ void k_healpix(int level, int64_t first, int64_t count, double* out) 
   out[3 * q + 2] = z;
 }
 
+__global__ void k_budget(const Accum* acc, nrt_budget* out, uint64_t* dropped, double emitted,
+                         uint64_t spawned, int l_max) {
+  if (threadIdx.x != 0) return;
+  nrt_budget b;
+  b.emitted = emitted;
+  b.absorbed = acc->absorbed;
+  b.escaped = acc->escaped;
+  b.truncated = acc->truncated;
+  b.segments = acc->segments;
+  b.rays = 0;
+  b.splits = 0;
+  for (int l = 0; l <= NRT_MAX_LEVEL; ++l) {
+    const uint64_t k = l == 0 ? spawned : (l <= l_max ? uint64_t(acc->out_count[l]) : 0);
+    b.rays_per_level[l] = k;
+    b.rays += k;
+    if (l > 0) b.splits += k / 4;
+  }
+  *out = b;
+  if (dropped) *dropped = acc->overflow;
+}
+
 int grid_for(int64_t items, int block, int cap) {
   int64_t g = (items + block - 1) / block;
   if (g < 1) g = 1;
@@ -945,6 +966,13 @@ hipError_t launch_march(const nrt_ctx* c, const MarchArgs& args, int64_t rays, h
   a.claim = c->tuning.claim > 0 ? c->tuning.claim : 128;
   a.refill_min = c->tuning.refill_min > 0 ? c->tuning.refill_min : 16;
   hipLaunchKernelGGL(march_kernel(c->desc), dim3(blocks), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_budget(const Accum* acc, nrt_budget* out, uint64_t* dropped, double emitted,
+                         int64_t spawned, int l_max, hipStream_t s) {
+  hipLaunchKernelGGL(k_budget, dim3(1), dim3(64), 0, s, acc, out, dropped, emitted,
+                     uint64_t(spawned), l_max);
   return hipGetLastError();
 }
 
