@@ -678,9 +678,9 @@ __device__ __forceinline__ void push_pending(unsigned long long* count, const Ra
   }
 }
 
-// Persistent march: every wavefront claims runs of A.claim rays of the
-// launch's range, refills idle lanes from its run once A.refill_min of them
-// are idle, advances every busy lane by one cell per step, and folds its LDS
+// Persistent march: every wavefront takes runs of A.claim rays of the
+// launch's range (its first by position, the rest from a shared counter),
+// refills idle lanes from its run once A.refill_min of them are idle, advances every busy lane by one cell per step, and folds its LDS
 // table into Gamma when half full.  A lane whose ray splits keeps the
 // children's start state in registers; the wavefront appends the children of
 // all pending splits to the next level's queue with one atomicAdd once 32 are
@@ -717,9 +717,16 @@ __attribute__((amdgpu_waves_per_eu((MIXED && POLY) ? 4 : 1, 8))) void k_march(Ma
     const int64_t k = int64_t(*A.count_src);
     total = k < A.in_cap ? k : A.in_cap;
   }
+  // Wavefront w starts with rays [w claim, (w+1) claim) of the launch's range
+  // without touching the shared counter, which hands out the runs after the
+  // first nwaves * claim.  A wavefront with no first run has nothing to do,
+  // so the idle part of a persistent grid (small levels) issues no atomics.
   const int64_t claim = A.claim;
-  int64_t pool = 0, pool_end = 0;  // wavefront-uniform run of claimed rays
-  bool exhausted = total <= 0;
+  const int64_t first_runs = int64_t(gridDim.x) * kWaves * claim;
+  int64_t pool = (int64_t(blockIdx.x) * kWaves + wave) * claim;  // wavefront-uniform run
+  int64_t pool_end = pool + claim < total ? pool + claim : total;
+  bool exhausted = pool >= total;
+  if (exhausted) pool = pool_end = 0;
   int fill = 0;                    // wavefront-uniform occupied line slots
   for (;;) {
     const uint64_t idle = __ballot(!busy);
@@ -729,7 +736,7 @@ __attribute__((amdgpu_waves_per_eu((MIXED && POLY) ? 4 : 1, 8))) void k_march(Ma
       if (pool == pool_end) {
         unsigned long long b = 0;
         if (lane == 0) b = atomicAdd(F.claim_ctr, static_cast<unsigned long long>(claim));
-        b = read_lane64(b, 0);
+        b = read_lane64(b, 0) + static_cast<unsigned long long>(first_runs);
         if (int64_t(b) >= total) {
           exhausted = true;
         } else {
@@ -814,7 +821,8 @@ __attribute__((amdgpu_waves_per_eu((MIXED && POLY) ? 4 : 1, 8))) void k_march(Ma
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && (red_u[0] != 0 || red_d[1][0] != 0.0 || red_d[2][0] != 0.0)) {
+    // a block that marched nothing and stopped no ray adds nothing
     atomicAdd(&A.acc->absorbed, red_d[0][0]);
     atomicAdd(&A.acc->escaped, red_d[1][0]);
     atomicAdd(&A.acc->truncated, red_d[2][0]);
