@@ -685,12 +685,14 @@ __device__ __forceinline__ void push_pending(unsigned long long* count, const Ra
 // children's start state in registers; the wavefront appends the children of
 // all pending splits to the next level's queue with one atomicAdd once 32 are
 // pending (or a pending lane splits again, or the run ends).
-// The mixed polychromatic march is held to 128 VGPRs (it fits with no
-// spills), which keeps 4 waves per SIMD as its LDS allows; every other
-// instantiation is left to the compiler.
+// The periodic mixed polychromatic march is held to 128 VGPRs (it fits with
+// no spills), which keeps 4 waves per SIMD as its LDS allows; every other
+// instantiation (the open-box ones would spill under the same cap) is left
+// to the compiler.
 template <bool MIXED, int CORR, bool PERIODIC, bool POLY>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu((MIXED && POLY) ? 4 : 1, 8))) void k_march(MarchArgs A) {
+__attribute__((amdgpu_waves_per_eu((MIXED && POLY && PERIODIC) ? 4 : 1, 8))) void k_march(
+    MarchArgs A) {
   using V = typename std::conditional<MIXED, float, double>::type;
   // per-wavefront deposit tables, reused for the budget reduction at the end
   using Tab = LineTable<V>;
@@ -723,7 +725,10 @@ __attribute__((amdgpu_waves_per_eu((MIXED && POLY) ? 4 : 1, 8))) void k_march(Ma
   // so the idle part of a persistent grid (small levels) issues no atomics.
   const int64_t claim = A.claim;
   const int64_t first_runs = int64_t(gridDim.x) * kWaves * claim;
-  int64_t pool = (int64_t(blockIdx.x) * kWaves + wave) * claim;  // wavefront-uniform run
+  // the run bounds are wavefront-uniform: derive them from a uniform wave
+  // index so that they stay in scalar registers
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+  int64_t pool = (int64_t(blockIdx.x) * kWaves + wave_u) * claim;
   int64_t pool_end = pool + claim < total ? pool + claim : total;
   bool exhausted = pool >= total;
   if (exhausted) pool = pool_end = 0;
