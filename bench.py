@@ -40,6 +40,11 @@ WORKLOADS = {  # name -> generator in workloads/ (configs 1-5 of the method's te
     "clustered-512-32768src": "config4",
     "late-reion-1024-262144src": "config5",
 }
+# ray slots per level queue: 2^25 (0.8 GB per level) fits every level of the
+# smaller workloads, so their pass is one graph replay; the 1024^3 pass is
+# host-driven in chunks of a quarter of a queue, and each chunk launch ends
+# in a tail of long rays, so fewer, larger chunks pay (2^27: 32 GB of queues)
+DEFAULT_CAPACITY = {"late-reion-1024-262144src": 1 << 27}
 
 
 def make_workload(name):
@@ -379,8 +384,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="lognormal-128-64src")
-    ap.add_argument("--capacity", type=int, default=1 << 25,
-                    help="ray slots per HEALPix level queue (24 B each)")
+    ap.add_argument("--capacity", type=int, default=0,
+                    help="ray slots per HEALPix level queue (24 B each); default 2^25, "
+                         "2^27 for the 1024^3 workload")
     ap.add_argument("--paths", default="mixed,fp64")
     ap.add_argument("--cpu-sources", type=int, default=64,
                     help="sources the oracle baseline traces (64: the whole 128^3 pass)")
@@ -429,6 +435,8 @@ def main():
         log(f"calibration copy: 3 x {args.calibrate_copy} MiB")
         del src, dst
     spectrum = parse_spectrum(args.spectrum)
+    if not args.capacity:
+        args.capacity = DEFAULT_CAPACITY.get(args.workload, 1 << 25)
     w = make_workload(args.workload)
     if args.corr_study:
         if "steps" not in w.extra:
