@@ -12,8 +12,10 @@
 // are FP64 in both precisions and use only correctly rounded + - * / (the
 // library is compiled with FP contraction off).  MIXED = true computes the
 // optical depth, attenuation and deposits in FP32 from an FP32 absorber and
-// tracks the transmitted fraction in FP64.  The march is instantiated per
-// precision, correction mode and boundary.
+// tracks the transmitted fraction in FP64.  POLY = true integrates the flux
+// over a source spectrum with the table of Phi(tau) = -ln F(tau) built at
+// context set-up (spectrum.hip).  The march is instantiated per precision,
+// correction mode, boundary and spectrum.
 #include <cfloat>
 #include <type_traits>
 
@@ -201,7 +203,8 @@ struct RayState {
   double o0, o1, o2, d0, d1, d2;
   double t0, t1, t2;
   double s, L;
-  double tau, P;    // FP64 path: optical depth, photons carried
+  double tau, P;    // optical depth (FP64 path; also the mixed polychromatic
+                    // path, at the threshold), photons carried (FP64 path)
   double T, absf;   // mixed path: transmitted fraction, absorbed fraction
   double r2s, sqo;  // split radius^2 and sqrt(pixel solid angle) of the level
   float s_rate;     // mixed path: L / h^3 in FP32
@@ -233,9 +236,10 @@ __device__ __forceinline__ SpecPos spec_pos(double tau) {
   return p;
 }
 
-// (p(x2) - p(x1)) / (x2 - x1) for p = c0 + c1 x + ... + c5 x^5, as
-// sum_k c_k h_{k-1}(x1, x2) with h_j the complete homogeneous polynomial of
-// degree j; free of cancellation, and p'(x1) when x2 = x1
+// (p(x2) - p(x1)) / (x2 - x1) for p = c0 + c1 x + ... + c5 x^5, given
+// c[0..4] = c1..c5, as sum_k c_k h_{k-1}(x1, x2) with h_j the complete
+// homogeneous polynomial of degree j; free of cancellation, and p'(x1) when
+// x2 = x1
 template <typename T>
 __device__ __forceinline__ T spec_slope(const T* c, T x1, T x2) {
   const T h1 = x1 + x2;
@@ -931,7 +935,7 @@ hipError_t launch_zero_accum(Accum* acc, hipStream_t s) {
 
 namespace {
 
-// the march instantiation for a precision, correction mode and boundary
+// the march instantiation for a precision, correction mode, boundary and spectrum
 using MarchKernel = void (*)(MarchArgs);
 
 template <bool MIXED, bool PERIODIC, bool POLY>
