@@ -150,6 +150,34 @@ def test_poly_injected_rays(gpu, orc, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_poly_injected_rays_full_size(gpu, orc, prec):
+    """Sampled outputs at the benchmark's size: 256 rays injected at random
+    points of the 128^3 workload's field with a 5e4 K blackbody, long enough
+    to cross the field several times (periodic, s_max = sqrt(3) n), every
+    crossed cell against the oracle."""
+    w = W.config2()
+    g = np.random.default_rng(77)
+    k = 256
+    o = g.random((k, 3)) * w.n
+    d = g.standard_normal((k, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    lev = g.integers(0, 10, k).astype(np.int32)
+    L = 10 ** g.uniform(44, 47, k)
+    kw = dict(periodic=True, n_min_ray=0.0, l_max=w.l_max, tau_max=w.tau_max, n_th=w.n_th,
+              spectrum=BB, spec_param=5e4)
+    ref, rb, _ = orc.trace_rays(orc.make_params(w.n, w.h_cm, **kw), w.n_H, w.x, o, d, lev, L)
+    ctx = gpu.init_grid(gpu.make_desc(w.n, w.h_cm, precision=prec, **kw), w.n_H, w.x,
+                        device="cuda:0", max_sources=1, ray_capacity=4096)
+    gamma, b = ctx.trace_rays_debug(o, d, lev, L)
+    ctx.destroy()
+    e_in, e_out = rel_err(gamma.cpu().numpy(), ref)
+    tol = 1e-9 if prec == 0 else 1e-4
+    assert e_in <= tol and e_out <= tol, (e_in, e_out)
+    assert b["segments"] == rb["segments"] and rb["segments"] > 256 * 100
+    assert budget_err(b, rb) <= (1e-9 if prec == 0 else 1e-6)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 def test_poly_fully_ionized_is_thin_table(gpu, orc, prec):
     """x = 1 everywhere: every deposit is the thin limit, Gamma_poly = G(0) Gamma_mono
     with G(0) the spectrum's mean cross-section over sigma0."""
