@@ -91,7 +91,8 @@ typedef struct {
   double sigma0;      /* cross-section at the threshold [cm^2], >= 0              */
   double n_min_ray;   /* N_min^ray of Eq. split_criterion, >= 0; 0 never splits   */
   int32_t l_max;      /* HEALPix level cap, 0 .. NRT_MAX_LEVEL                    */
-  double tau_max;     /* optical-depth cap, > 0                                   */
+  double tau_max;     /* optical-depth cap, > 0 (with a spectrum: a ray stops once
+                         F(tau) <= e^{-tau_max}, see nrt_spectrum)                */
   double n_th;        /* neighbour density threshold [cm^-3] (Eq. new_correction) */
   int32_t corr;       /* nrt_corr                                                 */
   int32_t precision;  /* nrt_precision                                            */
