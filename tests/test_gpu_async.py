@@ -117,6 +117,8 @@ def test_async_reports_dropped_rays(gpu):
     ctx.destroy()
 
 
+# the refused call enqueues nothing, so the recorded graph is empty and torch says so
+@pytest.mark.filterwarnings("ignore:The CUDA Graph is empty")
 def test_async_refuses_unsynchronised_sources_under_capture(gpu):
     import torch
     s = torch.cuda.Stream()
