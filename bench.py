@@ -45,6 +45,10 @@ WORKLOADS = {  # name -> generator in workloads/ (configs 1-5 of the method's te
 # host-driven in chunks of a quarter of a queue, and each chunk launch ends
 # in a tail of long rays, so fewer, larger chunks pay (2^27: 32 GB of queues)
 DEFAULT_CAPACITY = {"late-reion-1024-262144src": 1 << 27}
+# launch parameters (refill_min, claim) that nrt_autotune picked for these
+# workloads on MI355X, for both paths; the others keep the library's defaults
+# (16, 128), which it picked for the 256^3 workload.  --tune runs it again.
+TUNED = {"lognormal-128-64src": (32, 64), "clustered-512-32768src": (16, 256)}
 
 
 def make_workload(name):
@@ -82,7 +86,7 @@ def subset_indices(m, k, seed=11):
 
 
 def run_path(nrt, w, precision, steps, warmup, capacity, graph=0, sources=0, tune=False,
-             spectrum=(0, 0.0)):
+             spectrum=(0, 0.0), tuned=None):
     """Time `steps` trace passes (after `warmup` untimed ones) of one
     arithmetic path.  Merging workloads merge first (timed on its own); with
     `sources`, a seeded subset of the (merged) catalogue is traced."""
@@ -107,9 +111,11 @@ def run_path(nrt, w, precision, steps, warmup, capacity, graph=0, sources=0, tun
         ctx.clear_sources()
         ctx.add_sources(p[idx], f[idx])
         m_traced = len(idx)
-    ctx.set_tuning(graph=graph)
+    refill, claim = tuned if tuned else (0, 0)
+    ctx.set_tuning(refill_min=refill, claim=claim, graph=graph)
     gamma = torch.empty((w.n,) * 3, dtype=torch.float64, device="cuda:0")
-    tuning = None
+    tuning = ({"refill_min": refill, "claim": claim, "picked_by": "nrt_autotune, frozen in bench.py"}
+              if tuned else None)
     if tune:
         t = ctx.autotune(passes=1, gamma=gamma)
         tuning = dict(t)
@@ -450,7 +456,7 @@ def main():
     for path in args.paths.split(","):
         prec = nrt.MIXED if path == "mixed" else nrt.FP64
         r = run_path(nrt, w, prec, args.steps, args.warmup, args.capacity, args.graph,
-                     args.sources, args.tune, spectrum)
+                     args.sources, args.tune, spectrum, TUNED.get(args.workload))
         r["segments_per_s_kernel"] = r["segments_per_step"] * args.steps / (
             r["kernel_ms_total"] / 1e3)
         res[path] = r
