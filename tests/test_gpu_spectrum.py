@@ -225,6 +225,7 @@ def test_poly_bench_workload_invariants(gpu, prec):
     (conservative correction), rays go at least as far as monochromatic ones
     (F(tau) >= e^{-tau} since sigma_nu <= sigma_0), and the mixed path is
     within 1e-4 of the FP64 one."""
+    import bench
     w = W.config2()
     res = {}
     for kind, p in ((0, 0), (BB, 0), (BB, prec)):
@@ -235,6 +236,8 @@ def test_poly_bench_workload_invariants(gpu, prec):
                              n_th=w.n_th, spectrum=kind, spec_param=5e4)
         ctx = gpu.init_grid(desc, w.n_H, w.x, device="cuda:0", max_sources=len(w.ndot),
                             ray_capacity=1 << 25)
+        refill, claim = bench.TUNED.get(w.name, (0, 0))  # bench.py's launch parameters
+        ctx.set_tuning(refill_min=refill, claim=claim)
         ctx.add_sources(w.pos, w.ndot)
         g, _ = ctx.trace_step()
         g, b = ctx.trace_step(g)

@@ -55,15 +55,19 @@ BENCH_CAPACITY = 1 << 25  # ray slots per level queue in bench.py
 
 
 def run_gpu_replayed(gpu, w, prec, pos=None, ndot=None, merge=False):
-    """The workload as bench.py times it: 2^25-slot level queues, one eager
-    pass, then the captured device-driven pass replayed; returns the
-    replayed pass's Gamma and budget (and the traced catalogue when merging)."""
+    """The workload as bench.py times it: 2^25-slot level queues, the launch
+    parameters bench.py sets for it, one eager pass, then the captured
+    device-driven pass replayed; returns the replayed pass's Gamma and budget
+    (and the traced catalogue when merging)."""
+    import bench
     pos = w.pos if pos is None else pos
     ndot = w.ndot if ndot is None else ndot
     desc = gpu.make_desc(w.n, w.h_cm, precision=prec, periodic=w.periodic, n_min_ray=w.n_min_ray,
                          l_max=w.l_max, tau_max=w.tau_max, n_th=w.n_th)
     ctx = gpu.init_grid(desc, w.n_H, w.x, device="cuda:0", max_sources=len(ndot),
                         ray_capacity=BENCH_CAPACITY)
+    refill, claim = bench.TUNED.get(w.name, (0, 0))
+    ctx.set_tuning(refill_min=refill, claim=claim)
     ctx.add_sources(pos, ndot)
     cat = None
     if merge:
