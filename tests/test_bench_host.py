@@ -26,6 +26,13 @@ def test_parse_spectrum():
             bench.parse_spectrum(bad)
 
 
+def test_launch_params():
+    assert bench.launch_params("lognormal-128-64src") == (32, 64)
+    assert bench.launch_params("lognormal-128-64src", 1) == (64, 64)
+    assert bench.launch_params("clustered-512-32768src", 1) == (16, 256)
+    assert bench.launch_params("lognormal-256-4096src-bubbles") is None
+
+
 def test_roofline_arithmetic():
     res = dict(segments_per_s_kernel=5e10, avg_launch_ms=2.0, launches=20,
                segments_per_step=10 ** 9, steps=2, graph=True)

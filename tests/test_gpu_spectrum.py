@@ -236,7 +236,7 @@ def test_poly_bench_workload_invariants(gpu, prec):
                              n_th=w.n_th, spectrum=kind, spec_param=5e4)
         ctx = gpu.init_grid(desc, w.n_H, w.x, device="cuda:0", max_sources=len(w.ndot),
                             ray_capacity=1 << 25)
-        refill, claim = bench.TUNED.get(w.name, (0, 0))  # bench.py's launch parameters
+        refill, claim = bench.launch_params(w.name, kind) or (0, 0)  # bench.py's
         ctx.set_tuning(refill_min=refill, claim=claim)
         ctx.add_sources(w.pos, w.ndot)
         g, _ = ctx.trace_step()

@@ -66,7 +66,7 @@ def run_gpu_replayed(gpu, w, prec, pos=None, ndot=None, merge=False):
                          l_max=w.l_max, tau_max=w.tau_max, n_th=w.n_th)
     ctx = gpu.init_grid(desc, w.n_H, w.x, device="cuda:0", max_sources=len(ndot),
                         ray_capacity=BENCH_CAPACITY)
-    refill, claim = bench.TUNED.get(w.name, (0, 0))
+    refill, claim = bench.launch_params(w.name) or (0, 0)
     ctx.set_tuning(refill_min=refill, claim=claim)
     ctx.add_sources(pos, ndot)
     cat = None
