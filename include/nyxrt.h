@@ -255,9 +255,11 @@ nrt_status nrt_set_tuning(nrt_ctx* ctx, const nrt_tuning* t);
 nrt_status nrt_get_tuning(const nrt_ctx* ctx, nrt_tuning* t);
 
 /* Autotuner: run one trace pass (into gamma_scratch, device n^3 FP64) per
-   candidate parameter set, time the march kernels with HIP events, keep the
-   fastest in the context and return it in *best (host).  `passes` repeats
-   each candidate (>= 1).  Uses the context's current grid and sources. */
+   candidate parameter set (refill_min 8, 16, 32, 64 x claim 0, 64, 256 x
+   blocks_per_cu as many as fit or one fewer), time the march kernels with
+   HIP events, keep the fastest in the context and return it in *best (host).
+   `passes` repeats each candidate (>= 1).  Uses the context's current grid
+   and sources. */
 nrt_status nrt_autotune(nrt_ctx* ctx, double* gamma_scratch, int32_t passes, nrt_tuning* best);
 
 /* Average duration [ms] of the march kernel launches of the last pass,

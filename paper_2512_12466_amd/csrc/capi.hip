@@ -835,7 +835,9 @@ nrt_status nrt_autotune(nrt_ctx* c, double* gamma_scratch, int32_t passes, nrt_t
   const nrt_tuning keep = c->tuning;
   std::vector<nrt_tuning> cand;
   const int max_bpc = std::max(1, c->march_blocks_per_cu);
-  for (int refill : {4, 8, 16, 32})
+  // refill 64: a wavefront refills only once drained (the best choice where
+  // the rays of a run live equally long)
+  for (int refill : {8, 16, 32, 64})
     for (int claim : {0, 64, 256})
       for (int bpc : {0, std::max(1, max_bpc - 1)}) {
         if (bpc != 0 && bpc == max_bpc) continue;
