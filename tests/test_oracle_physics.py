@@ -233,3 +233,85 @@ def test_correction_variant_identities(orc):
     a = (1 - x) * nH
     dep = lambda g: (g * a * h ** 3).sum()
     assert dep(g_sq) < dep(g_lin) < b_lin["absorbed"]
+
+
+def test_tau_max_stop_at_the_boundary(orc):
+    """Alg. functors, ray_fltr: a monochromatic ray stops at the first cell
+    boundary where its optical depth reaches tau_max (tested before the
+    advance, >= not >), and its remaining photons L e^{-tau} are booked as
+    truncated, not escaped.  One ray along +x from the plane x = 0 through a
+    uniform open box with sigma0 = h = 1 and a = 1/2, so that every cell adds
+    exactly dtau = 1/2 and the optical depth at boundary k is exactly k/2:
+    the ray stops after k = min{k : k/2 >= tau_max} segments."""
+    n = 64
+    nH, x = np.full((n, n, n), 0.5), np.zeros((n, n, n))
+    L = 1e48
+    for tau_max, k in ((3.0, 6), (2.7, 6), (3.2, 7), (0.5, 1), (0.4, 1)):
+        p = orc.make_params(n, 1.0, periodic=False, sigma0=1.0, n_min_ray=0.0,
+                            corr=orc.CORR_NONE, tau_max=tau_max)
+        gamma, b, log = orc.trace_rays(p, nH, x, np.array([[0.0, 32.5, 32.5]]),
+                                       np.array([[1.0, 0.0, 0.0]]), 0, L, max_log=n)
+        assert b["segments"] == k, tau_max
+        assert [tuple(v) for v in log["ijk"]] == [(c, 32, 32) for c in range(k)]
+        assert b["escaped"] == 0.0
+        assert b["truncated"] == pytest.approx(L * math.exp(-0.5 * k), rel=1e-14)
+        assert b["absorbed"] == pytest.approx(L * -math.expm1(-0.5 * k), rel=1e-14)
+        # cell c absorbs L e^{-c/2} (1 - e^{-1/2}); Gamma = dN / (a h^3)
+        expect = L * np.exp(-0.5 * np.arange(k)) * -math.expm1(-0.5) / 0.5
+        np.testing.assert_allclose(gamma[32, 32, :k], expect, rtol=1e-14)
+        assert np.count_nonzero(gamma) == k
+
+
+def _first_crossing_beyond(o, d, r):
+    """Smallest plane crossing t = (plane - o_a) / d_a of the line o + t d
+    with t^2 > r^2 (the cell boundary where a ray first needs to split)."""
+    best = math.inf
+    for a in range(3):
+        if d[a] == 0.0:
+            continue
+        # planes between o_a and o_a + (r + 2) d_a, on the side the ray travels
+        lo = math.floor(min(o[a], o[a] + (r + 2) * d[a])) - 1
+        hi = math.ceil(max(o[a], o[a] + (r + 2) * d[a])) + 1
+        for plane in range(lo, hi + 1):
+            t = (plane - o[a]) / d[a]
+            if t > 0 and t * t > r * r:
+                best = min(best, t)
+    return best
+
+
+def test_l_max_truncates_rays_that_need_to_split(orc):
+    """Alg. functors, ray_fltr with the reading that a ray at level l_max
+    marches until it would need to split and is then terminated into the
+    truncated term.  In the thin uniform open box of test_split_tree_counts
+    every ray up to level 5 reaches its split radius inside the box, so with
+    l_max = 4 levels 0..4 hold exactly 12 * 4^l rays, no ray reaches level
+    5, and each of the 3072 level-4 rays carries Ndot / 3072 and stops at the
+    first cell boundary s beyond its split radius R_split(4), with optical
+    depth kappa s (kappa = sigma0 a h per cell)."""
+    n = 64
+    kappa = 1e-3
+    h = kappa / (SIG * 1e-3)
+    nH, x = _uniform(n)
+    src = np.array([32.5, 32.5, 32.5])
+    Nd = 1e50
+    lmax = 4
+    p = orc.make_params(n, h, periodic=False, n_min_ray=4.0, l_max=lmax, tau_max=30.0)
+    gamma, b = orc.trace(p, nH, x, src[None], [Nd])
+    assert b["rays_per_level"][:lmax + 1] == [12 * 4 ** l for l in range(lmax + 1)]
+    assert b["rays_per_level"][lmax + 1:] == [0] * (len(b["rays_per_level"]) - lmax - 1)
+    assert b["splits"] == sum(12 * 4 ** l for l in range(lmax))
+    r4 = 1.0 / math.sqrt(4.0 * 4 * math.pi / (12 * 4 ** lmax))
+    assert r4 + math.sqrt(3) < 31.5
+    dirs = orc.healpix_dirs(lmax)
+    s_stop = np.array([_first_crossing_beyond(src, d, r4) for d in dirs])
+    assert np.all((s_stop > r4) & (s_stop <= r4 + math.sqrt(3)))
+    expect_T = (Nd / (12 * 4 ** lmax)) * np.exp(-kappa * s_stop).sum()
+    assert b["truncated"] == pytest.approx(expect_T, rel=1e-12)
+    assert b["escaped"] == 0.0
+    assert b["absorbed"] == pytest.approx(Nd - expect_T, rel=1e-12)
+    # nothing is deposited beyond the level-4 stop radius
+    c = np.arange(n) + 0.5
+    r = np.sqrt((c[None, None, :] - src[0]) ** 2 + (c[None, :, None] - src[1]) ** 2 +
+                (c[:, None, None] - src[2]) ** 2)
+    assert gamma[r > s_stop.max() + math.sqrt(3)].max() == 0.0
+    assert gamma[r < r4 - math.sqrt(3)].min() > 0.0
