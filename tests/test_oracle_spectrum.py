@@ -125,7 +125,8 @@ def test_fully_ionized_grid_scales_by_mean_cross_section(orc):
     np.testing.assert_allclose(poly, G0[0] * mono, rtol=1e-13, atol=0)
     assert bp["segments"] == bm["segments"] and bp["rays"] == bm["rays"]
     assert bp["absorbed"] == 0.0
-    assert bp["escaped"] + bp["truncated"] == pytest.approx(bp["emitted"], rel=1e-13)
+    # E = A + X + T up to the FP64 rounding of summing ~5e4 rays' photons
+    assert bp["escaped"] + bp["truncated"] == pytest.approx(bp["emitted"], rel=1e-12)
 
 
 def test_single_ray_closed_form_deposit(orc):

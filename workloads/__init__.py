@@ -15,10 +15,14 @@ normalisation.
 Seeds: numpy ``default_rng(12466 + 100 * cfg + stream)``; stream 0 = density,
 1 = source positions, 2 = luminosities, 3 = bubbles.
 """
+import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 from typing import Optional
 
 import numpy as np
+import scipy.fft as sfft
 
 SEED_BASE = 12466
 KPC_CM = 3.0856775814913673e21
@@ -42,36 +46,79 @@ def rng(cfg: int, stream: int) -> np.random.Generator:
     return np.random.default_rng(SEED_BASE + 100 * cfg + stream)
 
 
+_SLAB = 16  # planes of the first axis per generation task
+
+
+def _threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _over_slabs(n: int, fn) -> list:
+    """fn(lo, hi) for the slabs [lo, hi) of the first axis, on a thread pool
+    (numpy releases the GIL in bulk array work); results in slab order."""
+    spans = [(lo, min(n, lo + _SLAB)) for lo in range(0, n, _SLAB)]
+    with ThreadPoolExecutor(_threads()) as ex:
+        return list(ex.map(lambda sp: fn(*sp), spans))
+
+
 def gaussian_field(n: int, gen: np.random.Generator, slope: float = -2.0,
                    log=None) -> np.ndarray:
     """Periodic Gaussian random field with power spectrum P(k) ~ k^slope,
-    zero mean, unit variance, shape (n,n,n) indexed [k,j,i]."""
+    zero mean, unit variance, shape (n,n,n) indexed [k,j,i].
+
+    White noise comes from one child generator per slab of _SLAB planes
+    (seeded from `gen`), so the field does not depend on the thread count."""
     log = log or (lambda *a: None)
-    white = gen.standard_normal((n, n, n))
-    fk = np.fft.rfftn(white)
+    seeds = np.random.SeedSequence(int(gen.integers(0, 2 ** 63))).spawn((n + _SLAB - 1) // _SLAB)
+    white = np.empty((n, n, n))
+
+    def fill(lo, hi):
+        np.random.default_rng(seeds[lo // _SLAB]).standard_normal(out=white[lo:hi])
+    _over_slabs(n, fill)
+    log("gaussian field: white noise done")
+    fk = sfft.rfftn(white, workers=_threads())
     del white
     log("gaussian field: forward FFT done")
     kx = np.fft.fftfreq(n) * n
     kz = np.fft.rfftfreq(n) * n
-    # sqrt(P) = k^(slope/2), applied one slab of the first axis at a time
-    # (the same elementwise operations as on the whole array, less memory)
-    for a in range(n):
-        k2 = kx[a] ** 2 + kx[:, None] ** 2 + kz[None, :] ** 2
-        with np.errstate(divide="ignore"):
-            fk[a] *= np.where(k2 > 0, k2 ** (slope / 4.0), 0.0)
+
+    # sqrt(P) = k^(slope/2), applied one plane of the first axis at a time
+    def shape(lo, hi):
+        for a in range(lo, hi):
+            k2 = kx[a] ** 2 + kx[:, None] ** 2 + kz[None, :] ** 2
+            with np.errstate(divide="ignore"):
+                fk[a] *= np.where(k2 > 0, k2 ** (slope / 4.0), 0.0)
+    _over_slabs(n, shape)
     log("gaussian field: spectrum applied")
-    g = np.fft.irfftn(fk, s=(n, n, n), axes=(0, 1, 2))
+    g = sfft.irfftn(fk, s=(n, n, n), axes=(0, 1, 2), workers=_threads())
     del fk
     log("gaussian field: inverse FFT done")
-    g -= g.mean()
-    g /= g.std()
+    # zero mean, unit variance: per-slab sums combined in slab order
+    mean = sum(_over_slabs(n, lambda lo, hi: float(g[lo:hi].sum()))) / g.size
+
+    def centre(lo, hi):
+        g[lo:hi] -= mean
+        return float(np.square(g[lo:hi]).sum())
+    std = math.sqrt(sum(_over_slabs(n, centre)) / g.size)
+
+    def scale(lo, hi):
+        g[lo:hi] /= std
+    _over_slabs(n, scale)
     return g
 
 
 def lognormal_density(n: int, mean: float, sigma_ln: float, gen, log=None) -> np.ndarray:
     """n_H = mean * exp(sigma g - sigma^2 / 2): lognormal with the given mean."""
     g = gaussian_field(n, gen, log=log)
-    return mean * np.exp(sigma_ln * g - 0.5 * sigma_ln ** 2)
+
+    def ln(lo, hi):
+        v = g[lo:hi]
+        v *= sigma_ln
+        v -= 0.5 * sigma_ln ** 2
+        np.exp(v, out=v)
+        v *= mean
+    _over_slabs(n, ln)
+    return g
 
 
 def lognormal_values(m: int, mean: float, sigma_ln: float, gen) -> np.ndarray:
@@ -98,24 +145,32 @@ def clustered_cells(n: int, n_clusters: int, per_cluster: int, sigma_cells: floa
 def paint_bubbles(n: int, centres: np.ndarray, radii: np.ndarray, x_in: float = 1.0 - 1e-4,
                   periodic: bool = True, out: Optional[np.ndarray] = None) -> np.ndarray:
     """Ionized fraction: x_in in every cell whose centre lies within a
-    bubble (min-image distance <= r), 0 elsewhere.  Shape (n,n,n) [k,j,i]."""
+    bubble (min-image distance <= r), 0 elsewhere.  Shape (n,n,n) [k,j,i].
+    Threads paint disjoint slabs of the first axis, so the result does not
+    depend on the thread count (every painted cell gets the same value)."""
     x = np.zeros((n, n, n)) if out is None else out
+    boxes = []
     for c, r in zip(np.asarray(centres, float), np.asarray(radii, float)):
         lo = np.floor(c - r - 1).astype(int)
         hi = np.ceil(c + r + 1).astype(int)
         ii = [np.arange(lo[a], hi[a] + 1) for a in range(3)]
         if not periodic:
             ii = [v[(v >= 0) & (v < n)] for v in ii]
+        if not all(v.size for v in ii):
+            continue
         d = [(v + 0.5 - c[a]) ** 2 for a, v in enumerate(ii)]
         inside = (d[2][:, None, None] + d[1][None, :, None] + d[0][None, None, :]) <= r * r
-        if all(v.size and v[0] >= 0 and v[-1] < n for v in ii):  # no wrap: plain slices
-            view = x[ii[2][0]:ii[2][-1] + 1, ii[1][0]:ii[1][-1] + 1, ii[0][0]:ii[0][-1] + 1]
-            view[inside] = x_in
-            continue
-        kk, jj, iq = [v % n for v in (ii[2], ii[1], ii[0])]
-        sub = x[np.ix_(kk, jj, iq)]
-        sub[inside] = x_in
-        x[np.ix_(kk, jj, iq)] = sub
+        boxes.append(([v % n for v in (ii[2], ii[1], ii[0])], inside))
+
+    def paint(k0, k1):
+        for (kk, jj, iq), inside in boxes:
+            sel = (kk >= k0) & (kk < k1)
+            if not sel.any():
+                continue
+            sub = x[np.ix_(kk[sel], jj, iq)]
+            sub[inside[sel]] = x_in
+            x[np.ix_(kk[sel], jj, iq)] = sub
+    _over_slabs(n, paint)
     return x
 
 
@@ -124,15 +179,25 @@ def _radius_scale(n, centres, u, share, gen, samples=400000, log=None):
     volume, from a Monte-Carlo sample of cell centres: a sample point lies
     in some bubble iff min_b d_b / u_b <= rho (periodic min-image distance
     d_b), so the covered share at rho is the share of points whose minimum
-    is at most rho, and rho is that minimum's `share`-quantile."""
+    is at most rho, and rho is that minimum's `share`-quantile.  Bubbles are
+    taken in blocks on a thread pool; a minimum does not depend on order."""
     pts = np.floor(gen.random((samples, 3)) * n) + 0.5
-    q = np.full(samples, np.inf)
-    for b, (c, ub) in enumerate(zip(np.asarray(centres, float), np.asarray(u, float))):
-        d = np.abs(pts - c)
-        d = np.minimum(d, n - d)
-        np.minimum(q, np.sqrt((d * d).sum(1)) / ub, out=q)
-        if log and (b + 1) % 1000 == 0:
-            log(f"radius scale: {b + 1} bubbles")
+    centres = np.asarray(centres, float)
+    u = np.asarray(u, float)
+    block = 32
+
+    def part(b0):
+        q = np.full(samples, np.inf)
+        for c, ub in zip(centres[b0:b0 + block], u[b0:b0 + block]):
+            d = np.abs(pts - c)
+            d = np.minimum(d, n - d)
+            np.minimum(q, np.sqrt((d * d).sum(1)) / ub, out=q)
+        return q
+    with ThreadPoolExecutor(_threads()) as ex:
+        parts = list(ex.map(part, range(0, centres.shape[0], block)))
+    q = np.minimum.reduce(parts)
+    if log:
+        log(f"radius scale: {centres.shape[0]} bubbles")
     return float(np.quantile(q, share, method="inverted_cdf"))
 
 
