@@ -47,10 +47,13 @@ typedef enum {
 } nrt_status;
 
 /* Arithmetic of the march (a3-a4).  Both paths take every discrete decision
-   (cell crossing, split, face choice, thresholds) in FP64 with the same
-   operations, so they execute the same segments; NRT_MIXED computes the
-   absorber, optical depth, attenuation and deposits in FP32 and keeps the
-   photon budget in FP64. */
+   (cell crossing, split, face choice, the tau_max stop, thresholds) in FP64
+   with the same operations, so they execute the same segments, rays and
+   splits: the optical depth that the tau_max stop reads is accumulated in
+   FP64 from the FP64 absorber in both.  NRT_MIXED computes the attenuation,
+   the deposits and the correction factors in FP32 (the neighbour's absorber
+   from an FP32 copy) and keeps the transmitted fraction and the photon
+   budget in FP64. */
 typedef enum { NRT_FP64 = 0, NRT_MIXED = 1 } nrt_precision;
 
 /* Overlap correction (Sec. "Geometric correction"). */
@@ -72,7 +75,10 @@ typedef enum {
    -F'(tau) for cells with no absorber (the optically thin table of the
    footnote in Sec. "Numerical instability for low n_H neighbor cells").  The
    cap tau_max then applies to the whole spectrum: a ray stops once
-   F(tau) <= e^{-tau_max}, the share a monochromatic ray keeps at tau_max. */
+   F(tau) <= e^{-tau_max}, the share a monochromatic ray keeps at tau_max.
+   The library takes that decision on the threshold optical depth, against
+   the depth at which its FP64 table of -ln F reaches tau_max (found once at
+   nrt_init_grid), so both precisions take it alike. */
 typedef enum {
   NRT_SPEC_MONO = 0,      /* every photon at nu_0 (spec_param ignored)           */
   NRT_SPEC_BLACKBODY = 1, /* photon rate per frequency ~ nu^2 / (e^{h nu/kT} - 1);

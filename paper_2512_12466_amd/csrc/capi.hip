@@ -15,7 +15,14 @@ using nrt::RayQueue;
 
 namespace {
 
-thread_local std::string g_init_error;
+// message of the last failure that has no context (fixed storage, so that
+// setting it allocates nothing)
+thread_local char g_init_error[512];
+
+void set_init_error(const char* msg) {
+  std::strncpy(g_init_error, msg, sizeof(g_init_error) - 1);
+  g_init_error[sizeof(g_init_error) - 1] = 0;
+}
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -23,7 +30,7 @@ nrt_status fail(nrt_ctx* c, nrt_status s, const std::string& msg) {
   if (c)
     c->err = msg;
   else
-    g_init_error = msg;
+    set_init_error(msg.c_str());
   return s;
 }
 
@@ -37,29 +44,30 @@ nrt_status hip_fail(nrt_ctx* c, hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_fail((ctx), e_, #expr); \
   } while (0)
 
-bool check_desc(const nrt_grid_desc* d, std::string& why) {
-  if (!d) return why = "desc is NULL", false;
-  if (d->n < 1 || d->n > 4096) return why = "n must be in [1, 4096]", false;
-  if (!(d->h_cm > 0.0) || !std::isfinite(d->h_cm)) return why = "h_cm must be > 0", false;
-  if (!(d->sigma0 >= 0.0) || !std::isfinite(d->sigma0)) return why = "sigma0 must be >= 0", false;
+// the reason a grid descriptor is invalid, or NULL
+const char* check_desc(const nrt_grid_desc* d) {
+  if (!d) return "desc is NULL";
+  if (d->n < 1 || d->n > 4096) return "n must be in [1, 4096]";
+  if (!(d->h_cm > 0.0) || !std::isfinite(d->h_cm)) return "h_cm must be > 0";
+  if (!(d->sigma0 >= 0.0) || !std::isfinite(d->sigma0)) return "sigma0 must be >= 0";
   if (!(d->n_min_ray >= 0.0) || !std::isfinite(d->n_min_ray))
-    return why = "n_min_ray must be >= 0", false;
-  if (d->l_max < 0 || d->l_max > NRT_MAX_LEVEL) return why = "l_max out of range", false;
-  if (!(d->tau_max > 0.0)) return why = "tau_max must be > 0", false;
-  if (std::isnan(d->n_th)) return why = "n_th is NaN", false;
-  if (d->corr < NRT_CORR_NONE || d->corr > NRT_CORR_NAIVE) return why = "bad corr", false;
-  if (d->precision != NRT_FP64 && d->precision != NRT_MIXED) return why = "bad precision", false;
-  if (d->periodic != 0 && d->periodic != 1) return why = "periodic must be 0 or 1", false;
+    return "n_min_ray must be >= 0";
+  if (d->l_max < 0 || d->l_max > NRT_MAX_LEVEL) return "l_max out of range";
+  if (!(d->tau_max > 0.0)) return "tau_max must be > 0";
+  if (std::isnan(d->n_th)) return "n_th is NaN";
+  if (d->corr < NRT_CORR_NONE || d->corr > NRT_CORR_NAIVE) return "bad corr";
+  if (d->precision != NRT_FP64 && d->precision != NRT_MIXED) return "bad precision";
+  if (d->periodic != 0 && d->periodic != 1) return "periodic must be 0 or 1";
   if (d->spectrum == NRT_SPEC_BLACKBODY) {
     if (!(d->spec_param >= 1e3 && d->spec_param <= 1e7))
-      return why = "blackbody temperature must be in [1e3, 1e7] K", false;
+      return "blackbody temperature must be in [1e3, 1e7] K";
   } else if (d->spectrum == NRT_SPEC_POWERLAW) {
     if (!(d->spec_param >= 2.5 && d->spec_param <= 50.0))
-      return why = "power-law index must be in [2.5, 50]", false;
+      return "power-law index must be in [2.5, 50]";
   } else if (d->spectrum != NRT_SPEC_MONO) {
-    return why = "bad spectrum", false;
+    return "bad spectrum";
   }
-  return true;
+  return nullptr;
 }
 
 // Omega(l) = 4 pi / (12 4^l) (Eq. split_criterion); split iff s^2 > 1/(N_min Omega(l))
@@ -103,23 +111,8 @@ nrt_status upload_sources(nrt_ctx* c) {
 }
 
 MarchArgs base_args(const nrt_ctx* c, double* gamma) {
-  MarchArgs a;
-  std::memset(&a, 0, sizeof(a));
-  const nrt_grid_desc& d = c->desc;
-  a.n = d.n;
-  a.periodic = d.periodic;
-  a.corr = d.corr;
-  a.l_max = d.l_max;
-  a.h_cm = d.h_cm;
-  a.sigma0 = d.sigma0;
-  a.tau_max = d.tau_max;
-  a.s_max = d.periodic ? std::sqrt(3.0) * double(d.n) : INFINITY;
-  a.h3 = d.h_cm * d.h_cm * d.h_cm;
-  a.t_min = std::exp(-d.tau_max);
-  a.kf = float(d.sigma0 * d.h_cm);
-  a.a64 = c->a64;
-  a.a32 = c->a32;
-  a.gamma = gamma;
+  MarchArgs a = nrt::march_grid_args(c->desc, c->a64, c->a32, gamma, c->acc);
+  a.tau_stop = c->desc.spectrum != NRT_SPEC_MONO ? c->spec_tau_stop : c->desc.tau_max;
   a.src_pos = c->src_pos;
   a.src_l0 = c->src_l0;
   a.dirs = c->dirs;
@@ -127,9 +120,6 @@ MarchArgs base_args(const nrt_ctx* c, double* gamma) {
   a.spec_nint = c->spec_nint;
   a.spec64 = c->spec64;
   a.spec32 = c->spec32;
-  for (int l = 0; l <= nrt::kMaxLevel; ++l) a.sqrt_omega_tab[l] = c->sqrt_omega[l];
-  a.acc = c->acc;
-  a.lds_keys_fit = ((int64_t(d.n) * d.n * d.n) >> 3 < (int64_t(1) << 32) - 1) ? 1 : 0;
   return a;
 }
 
@@ -394,6 +384,38 @@ nrt_status prep_absorber(nrt_ctx* c, const double* x_field) {
 
 namespace nrt {
 
+const char* check_grid_desc(const nrt_grid_desc* d) { return check_desc(d); }
+
+void set_error(const char* msg) { set_init_error(msg); }
+
+MarchArgs march_grid_args(const nrt_grid_desc& d, const double* a64, const float* a32,
+                          double* gamma, Accum* acc) {
+  MarchArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = d.n;
+  a.periodic = d.periodic;
+  a.corr = d.corr;
+  a.l_max = d.l_max;
+  a.h_cm = d.h_cm;
+  a.sigma0 = d.sigma0;
+  a.tau_max = d.tau_max;
+  a.s_max = d.periodic ? std::sqrt(3.0) * double(d.n) : INFINITY;
+  a.h3 = d.h_cm * d.h_cm * d.h_cm;
+  a.tau_stop = d.tau_max;
+  a.kf = float(d.sigma0 * d.h_cm);
+  a.a64 = a64;
+  a.a32 = a32;
+  a.gamma = gamma;
+  a.dir_max_level = -1;  // no direction table: directions computed in the march
+  for (int l = 0; l <= kMaxLevel; ++l) {
+    const double omega = (4.0 * M_PI) / (12.0 * std::ldexp(1.0, 2 * l));
+    a.sqrt_omega_tab[l] = std::sqrt(omega);
+  }
+  a.acc = acc;
+  a.lds_keys_fit = ((int64_t(d.n) * d.n * d.n) >> 3 < (int64_t(1) << 32) - 1) ? 1 : 0;
+  return a;
+}
+
 Layout plan_layout(const nrt_grid_desc& d, int64_t max_sources, int64_t capacity) {
   Layout L;
   std::memset(&L, 0, sizeof(L));
@@ -407,8 +429,10 @@ Layout plan_layout(const nrt_grid_desc& d, int64_t max_sources, int64_t capacity
   off = align256(off + size_t(cells) * 8);
   L.x = off;
   off = align256(off + size_t(cells) * 8);
+  // FP64 absorber (both paths: the optical depth that carries the tau_max
+  // decision), then its FP32 copy (mixed path only)
   L.a = off;
-  off = align256(off + size_t(cells) * (d.precision == NRT_MIXED ? 4 : 8));
+  off = align256(off + size_t(cells) * (d.precision == NRT_MIXED ? 12 : 8));
   L.srcpos = off;
   off = align256(off + size_t(max_sources) * 24);
   L.srcl0 = off;
@@ -455,13 +479,12 @@ const char* nrt_status_str(nrt_status s) {
 }
 
 const char* nrt_last_error(const nrt_ctx* c) {
-  return c ? c->err.c_str() : g_init_error.c_str();
+  return c ? c->err.c_str() : g_init_error;
 }
 
 nrt_status nrt_workspace_bytes(const nrt_grid_desc* desc, int64_t max_sources,
                                int64_t ray_capacity, size_t* bytes) {
-  std::string why;
-  if (!check_desc(desc, why)) return fail(nullptr, NRT_ERR_ARG, why);
+  if (const char* why = check_desc(desc)) return fail(nullptr, NRT_ERR_ARG, why);
   if (max_sources < 0 || max_sources > (int64_t(1) << 31))
     return fail(nullptr, NRT_ERR_ARG, "max_sources out of range");
   if (ray_capacity < 4096 || ray_capacity > (int64_t(1) << 32))
@@ -493,7 +516,7 @@ nrt_status nrt_init_grid(nrt_ctx** out, const nrt_grid_desc* desc, const double*
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->ws = static_cast<char*>(workspace);
   auto bail = [&](nrt_status s) {
-    g_init_error = c->err;
+    set_init_error(c->err.c_str());
     nrt_destroy(c);
     return s;
   };
@@ -506,8 +529,9 @@ nrt_status nrt_init_grid(nrt_ctx** out, const nrt_grid_desc* desc, const double*
   const Layout& L = c->lay;
   c->n_H = reinterpret_cast<double*>(c->ws + L.n_H);
   c->x = reinterpret_cast<double*>(c->ws + L.x);
-  c->a64 = desc->precision == NRT_MIXED ? nullptr : reinterpret_cast<double*>(c->ws + L.a);
-  c->a32 = desc->precision == NRT_MIXED ? reinterpret_cast<float*>(c->ws + L.a) : nullptr;
+  c->a64 = reinterpret_cast<double*>(c->ws + L.a);
+  c->a32 = desc->precision == NRT_MIXED ? reinterpret_cast<float*>(c->ws + L.a + size_t(L.cells) * 8)
+                                        : nullptr;
   c->src_pos = reinterpret_cast<double*>(c->ws + L.srcpos);
   c->src_l0 = reinterpret_cast<double*>(c->ws + L.srcl0);
   c->dirs = reinterpret_cast<double*>(c->ws + L.dirs);
@@ -553,6 +577,14 @@ nrt_status nrt_init_grid(nrt_ctx** out, const nrt_grid_desc* desc, const double*
   if (desc->spectrum != NRT_SPEC_MONO) {
     st = nrt::build_spectrum_table(c);
     if (st) return bail(st);
+    double* stop = reinterpret_cast<double*>(c->scratch);
+    e = nrt::launch_spec_stop(c, stop);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&c->h_acc->absorbed, stop, sizeof(double), hipMemcpyDeviceToHost,
+                         c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return bail(hip_fail(c, e, "spectrum stop depth"));
+    c->spec_tau_stop = c->h_acc->absorbed;
   }
   *out = c;
   return NRT_OK;

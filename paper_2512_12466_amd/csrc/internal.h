@@ -18,9 +18,9 @@ constexpr int kBlock = 256;  // threads per block of the march kernels (4 waves)
 
 // One ray in a level queue (structure of arrays, 24 bytes per ray).  The
 // HEALPix level is the queue's, the rate follows from the source and level,
-// and the direction from (level, pix).  w is the optical depth tau (FP64
-// path) or the transmitted fraction exp(-tau) (mixed path); with a
-// polychromatic source it is the threshold optical depth in both paths.
+// and the direction from (level, pix).  w is the optical depth tau at the
+// ionization threshold, accumulated in FP64 in both precisions (it carries
+// the tau_max decision).
 struct RayQueue {
   uint32_t* src;
   uint32_t* pix;
@@ -74,13 +74,15 @@ struct MarchArgs {
   double h_cm, sigma0, tau_max, s_max, h3;
   double r2split;    // split iff s*s > r2split (this level)
   double sqrt_omega; // sqrt of the pixel solid angle (this level)
-  double t_min;      // exp(-tau_max): mixed-path and polychromatic termination threshold
+  double tau_stop;   // the ray stops once tau >= tau_stop: tau_max for a
+                     // monochromatic source; for a spectrum the threshold
+                     // optical depth at which Phi(tau) reaches tau_max
   float kf;          // (float)(sigma0 * h_cm)
   int32_t spec_nint;            // polychromatic: table intervals in use
   const SpecRec64* spec64;      // polychromatic table (FP64 path, and ray set-up)
   const SpecRec32* spec32;      // the same for the mixed path
   const double* a64; // absorber, sign bit set = not a usable neighbour
-  const float* a32;
+  const float* a32;  // its FP32 copy (mixed path: the neighbour's absorber)
   double* gamma;
   // sources
   const double* dirs;     // HEALPix directions (x, y, z) of levels 0..dir_max_level
@@ -126,6 +128,16 @@ struct Layout {
 
 Layout plan_layout(const nrt_grid_desc& d, int64_t max_sources, int64_t capacity);
 
+// march arguments that follow from the grid alone (no sources, queues or
+// direction table: the caller sets those); tau_stop is tau_max
+MarchArgs march_grid_args(const nrt_grid_desc& d, const double* a64, const float* a32,
+                          double* gamma, Accum* acc);
+
+// the reason a grid descriptor is invalid, or NULL (capi.hip)
+const char* check_grid_desc(const nrt_grid_desc* d);
+// set the message nrt_last_error(NULL) returns (fixed storage, no allocation)
+void set_error(const char* msg);
+
 }  // namespace nrt
 
 struct nrt_ctx {
@@ -155,6 +167,7 @@ struct nrt_ctx {
   nrt::SpecRec32* spec32;
   double* spec_nodes;  // m0, mean, variance at the table's nodes
   int32_t spec_nint;
+  double spec_tau_stop;  // threshold optical depth where Phi reaches tau_max
   double* src_pos;
   double* src_l0;
   nrt::RayQueue queue[nrt::kMaxLevel + 1];
@@ -180,11 +193,24 @@ namespace nrt {
 
 // trace.hip
 hipError_t launch_prep(nrt_ctx* c);
+// absorber (and its FP32 copy when a32 is non-null) from n_H and x, invalid
+// input cells counted in acc->invalid
+hipError_t launch_prep_fields(const double* n_H, const double* x, double n_th, int64_t ncell,
+                              double* a64, float* a32, Accum* acc, int cus, hipStream_t s);
+// the march on a persistent grid of at most cu_count * resident_per_cu blocks
+hipError_t launch_march_on(const nrt_grid_desc& d, int cu_count, int resident_per_cu,
+                           const nrt_tuning& t, const MarchArgs& a, int64_t rays,
+                           hipStream_t st);
+// l0[k] = ndot[k] / 12 on the device
+hipError_t launch_source_rates(const double* ndot, int64_t m, double* l0, hipStream_t s);
 hipError_t launch_zero(double* p, int64_t count, int cus, hipStream_t s);
 hipError_t launch_zero_accum(Accum* acc, hipStream_t s);
 hipError_t launch_march(const nrt_ctx* c, const MarchArgs& a, int64_t rays, hipStream_t st);
 hipError_t march_blocks_per_cu(const nrt_grid_desc& d, int* blocks);
 hipError_t launch_healpix(int level, int64_t first, int64_t count, double* out, hipStream_t s);
+// the threshold optical depth where a spectrum's Phi reaches tau_max, written
+// to one device double (the spectrum table must be built)
+hipError_t launch_spec_stop(const nrt_ctx* c, double* out);
 // budget of a device-driven pass into device memory: emitted and the spawn
 // count come from the host, the rest from the accumulator block
 hipError_t launch_budget(const Accum* acc, nrt_budget* out, uint64_t* dropped, double emitted,

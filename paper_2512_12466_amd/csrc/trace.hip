@@ -10,13 +10,18 @@
 //
 // Decisions (next cell, split, stop tests, face of the overlap correction)
 // are FP64 in both precisions and use only correctly rounded + - * / (the
-// library is compiled with FP contraction off).  MIXED = true computes the
-// optical depth, attenuation and deposits in FP32 from an FP32 absorber and
-// tracks the transmitted fraction in FP64.  POLY = true integrates the flux
+// library is compiled with FP contraction off).  The optical depth that the
+// tau_max stop reads is one of them: both precisions accumulate it in FP64
+// from the FP64 absorber by the same operations, so the two paths march the
+// same segments and split the same rays.  MIXED = true computes the
+// attenuation, the deposits and the correction factors in FP32 (the
+// neighbour's absorber from an FP32 copy) and tracks the transmitted
+// fraction in FP64.  POLY = true integrates the flux
 // over a source spectrum with the table of Phi(tau) = -ln F(tau) built at
 // context set-up (spectrum.hip).  The march is instantiated per precision,
 // correction mode, boundary and spectrum.
 #include <cfloat>
+#include <cmath>
 #include <type_traits>
 
 #include "healpix.h"
@@ -203,15 +208,12 @@ struct RayState {
   double o0, o1, o2, d0, d1, d2;
   double t0, t1, t2;
   double s, L;
-  double tau, P;    // optical depth (FP64 path; also the mixed polychromatic
-                    // path, at the threshold), photons carried (FP64 path)
-  double T, absf;   // mixed path: transmitted fraction, absorbed fraction
-  double r2s, sqo;  // split radius^2 and sqrt(pixel solid angle) of the level
+  double tau;       // optical depth at the threshold (FP64, both paths)
+  double P;         // photons carried (FP64 path)
+  double T;         // mixed path: transmitted fraction
   float s_rate;     // mixed path: L / h^3 in FP32
-  double a64;       // absorber of the current cell, loaded ahead (FP64 path)
-  float a32;        // the same for the mixed path
+  double a64;       // absorber of the current cell, loaded ahead
   int i0, i1, i2, w0, w1, w2;
-  int st0, st1, st2;
   int level;
   uint32_t src, pix;
 };
@@ -315,9 +317,8 @@ __device__ __forceinline__ V spec_rise(Args& A, double tau, V dtau, V& slope) {
 }
 
 // One ray of a launch as queued: source, HEALPix pixel, path length and
-// carried weight (optical depth in the FP64 path, transmitted fraction in the
-// mixed one, the threshold optical depth for a polychromatic source).  For
-// injected rays `src` holds the ray's index.
+// optical depth at the threshold.  For injected rays `src` holds the ray's
+// index.
 struct Entry {
   uint32_t src, pix;
   double s, w;
@@ -325,14 +326,14 @@ struct Entry {
 
 // Entry r of the launch: a virtual spawn index, a queue slot or an injected
 // ray's index.
-template <bool W_IS_T, typename Args>
+template <typename Args>
 __device__ __forceinline__ Entry load_entry(Args& A, int64_t r) {
   Entry e;
   if (A.level < 0) {
     e.src = uint32_t(r);
     e.pix = 0;
     e.s = 0.0;
-    e.w = W_IS_T ? 1.0 : 0.0;
+    e.w = 0.0;
   } else if (A.spawn) {
     if (r < (int64_t(1) << 32)) {
       const uint32_t r32 = uint32_t(r);
@@ -343,7 +344,7 @@ __device__ __forceinline__ Entry load_entry(Args& A, int64_t r) {
       e.pix = uint32_t(r % 12);
     }
     e.s = 0.0;
-    e.w = W_IS_T ? 1.0 : 0.0;
+    e.w = 0.0;
   } else {
     e.src = A.in.src[r];
     e.pix = A.in.pix[r];
@@ -369,8 +370,6 @@ __device__ int ray_init(RayState& R, Args& A, const Entry& e) {
     R.L = A.inj_L[r];
     R.level = A.inj_level[r];
     R.s = 0.0;
-    R.r2s = __builtin_inf();
-    R.sqo = A.sqrt_omega_tab[R.level];  // by value in the argument block
     R.src = R.pix = 0;
   } else {
     R.src = e.src;
@@ -389,35 +388,22 @@ __device__ int ray_init(RayState& R, Args& A, const Entry& e) {
     } else {
       healpix_dir(R.level, R.pix, R.d0, R.d1, R.d2);
     }
-    R.r2s = A.r2split;
-    R.sqo = A.sqrt_omega;
   }
   R.i0 = start_cell(R.o0, R.s, R.d0);
   R.i1 = start_cell(R.o1, R.s, R.d1);
   R.i2 = start_cell(R.o2, R.s, R.d2);
-  R.st0 = R.d0 > 0.0 ? 1 : (R.d0 < 0.0 ? -1 : 0);
-  R.st1 = R.d1 > 0.0 ? 1 : (R.d1 < 0.0 ? -1 : 0);
-  R.st2 = R.d2 > 0.0 ? 1 : (R.d2 < 0.0 ? -1 : 0);
   R.t0 = plane_t(R.o0, R.d0, R.i0);
   R.t1 = plane_t(R.o1, R.d1, R.i1);
   R.t2 = plane_t(R.o2, R.d2, R.i2);
-  if constexpr (POLY) {
-    R.tau = w;
-    const double T = exp(-spec_phi(A, w));
-    if (MIXED) {
-      R.T = T;
-      R.absf = 0.0;
-      R.s_rate = float(R.L / A.h3);
-    } else {
-      R.P = R.L * T;
-    }
-  } else if (MIXED) {
-    R.T = w;
-    R.absf = 0.0;
+  R.tau = w;
+  // transmitted share of the ray's photons: e^{-tau}, or e^{-Phi(tau)} for a
+  // spectrum (exactly 1 at a source)
+  const double T = w == 0.0 ? 1.0 : exp(POLY ? -spec_phi(A, w) : -w);
+  if (MIXED) {
+    R.T = T;
     R.s_rate = float(R.L / A.h3);
   } else {
-    R.tau = w;
-    R.P = R.L * exp(-R.tau);
+    R.P = R.L * T;
   }
   const int n = A.n;
   const bool out = R.i0 < 0 || R.i0 >= n || R.i1 < 0 || R.i1 >= n || R.i2 < 0 || R.i2 >= n;
@@ -425,11 +411,7 @@ __device__ int ray_init(RayState& R, Args& A, const Entry& e) {
   R.w0 = PERIODIC ? wrap_cell(R.i0, n) : R.i0;
   R.w1 = PERIODIC ? wrap_cell(R.i1, n) : R.i1;
   R.w2 = PERIODIC ? wrap_cell(R.i2, n) : R.i2;
-  const int64_t c0 = cell_index(R.w0, R.w1, R.w2, n);
-  if (MIXED)
-    R.a32 = A.a32[c0];
-  else
-    R.a64 = A.a64[c0];
+  R.a64 = A.a64[cell_index(R.w0, R.w1, R.w2, n)];
   return kGoOn;
 }
 
@@ -446,13 +428,12 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab
   const int n = A.n;
   constexpr bool open_box = !PERIODIC;
   if (PERIODIC && R.s >= A.s_max) return kEscaped;
-  // the optical-depth cap; for a spectrum, on the share of photons left
-  if constexpr (POLY) {
-    if (MIXED ? (R.T <= A.t_min) : (R.P <= R.L * A.t_min)) return kTruncated;
-  } else {
-    if (MIXED ? (R.T <= A.t_min) : (R.tau >= A.tau_max)) return kTruncated;
-  }
-  if (R.s * R.s > R.r2s) return R.level >= A.l_max ? kTruncated : kSplit;
+  // the optical-depth cap (for a spectrum: the threshold optical depth at
+  // which the share of photons left falls to e^{-tau_max})
+  if (R.tau >= A.tau_stop) return kTruncated;
+  // split radius^2 of the launch's level (injected rays never split)
+  const double r2s = A.level < 0 ? __builtin_inf() : A.r2split;
+  if (R.s * R.s > r2s) return R.level >= A.l_max ? kTruncated : kSplit;
   // next crossing: lowest axis wins exact ties
   int ax = 0;
   double tn = R.t0;
@@ -480,7 +461,8 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab
   float raw2_32 = 0.0f;
   if constexpr (CORR != NRT_CORR_NONE) {
     const double rm = 0.5 * (R.s + tn);
-    lpix = rm * R.sqo;
+    // sqrt of the pixel solid angle: sqrt(Omega(0)) 2^-level, exactly
+    lpix = rm * ldexp(A.sqrt_omega_tab[0], -R.level);
     int fax = 0, fdir;
     {
       const double m0 = R.o0 + rm * R.d0;
@@ -530,18 +512,22 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab
   }
 
   // ---- segment physics (Eq. lut_eqn, Eq. optical_depth) ----
-  double G64 = 0.0, a64 = 0.0;
+  // the cell's optical depth in FP64, the same operations in both paths
+  const double a64 = fabs(R.a64);
+  const double dl = ds * A.h_cm;
+  const double dtau64 = A.sigma0 * a64 * dl;
+  double G64 = 0.0;
   float G32 = 0.0f, a32 = 0.0f;
   if (MIXED) {
-    a32 = fabsf(R.a32);
+    a32 = float(a64);
     const float dsf = float(ds);
-    float dtau = A.kf * a32 * dsf;
+    float dtau = float(dtau64);
     float slope32 = 1.0f;
     if constexpr (POLY) {  // the whole spectrum's attenuation across the cell
       const float dtau0 = dtau;
       dtau = spec_rise<true>(A, R.tau, dtau0, slope32);
-      R.tau += double(dtau0);
     }
+    R.tau += dtau64;
     // surviving share e = exp(-dtau) from the hardware base-2 exponential
     // (1 ulp); absorbed share em = 1 - e, which for dtau < 1/8 comes from
     // its series (relative truncation error below dtau^5/720 < 5e-8) since
@@ -563,20 +549,19 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab
     }
     const float Tf = float(R.T);
     R.T = Tn;
-    R.absf += dT;
-    G32 = a32 > 0.0f ? (R.s_rate * float(dT)) * __builtin_amdgcn_rcpf(a32)
-                     : R.s_rate * Tf * (A.kf * dsf) * slope32;
+    acc.absorbed = fma(R.L, dT, acc.absorbed);
+    // an absorber below FP32's normal range takes the thin limit, which is
+    // exact there
+    G32 = a32 >= FLT_MIN ? (R.s_rate * float(dT)) * __builtin_amdgcn_rcpf(a32)
+                         : R.s_rate * Tf * (A.kf * dsf) * slope32;
   } else {
-    a64 = fabs(R.a64);
-    const double dl = ds * A.h_cm;
-    const double dtau = A.sigma0 * a64 * dl;
-    double rise = dtau, slope64 = 1.0;
-    if constexpr (POLY) rise = spec_rise<false>(A, R.tau, dtau, slope64);
+    double rise = dtau64, slope64 = 1.0;
+    if constexpr (POLY) rise = spec_rise<false>(A, R.tau, dtau64, slope64);
     const double dN = R.P * (-expm1(-rise));
     G64 = a64 > 0.0 ? dN / (a64 * A.h3) : R.P * A.sigma0 * dl * slope64 / A.h3;
     acc.absorbed += dN;
     R.P -= dN;
-    R.tau += dtau;
+    R.tau += dtau64;
   }
 
   // ---- overlap correction values (the decision above is FP64; the factor
@@ -626,7 +611,7 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab
     const int k0 = ax == 0, k1 = ax == 1, k2 = ax == 2;
     const double o_a = R.o0 * m0 + R.o1 * m1 + R.o2 * m2;
     const double d_a = R.d0 * m0 + R.d1 * m1 + R.d2 * m2;
-    const int st_a = R.st0 * k0 + R.st1 * k1 + R.st2 * k2;
+    const int st_a = d_a > 0.0 ? 1 : -1;
     const int i_a = R.i0 * k0 + R.i1 * k1 + R.i2 * k2 + st_a;
     const int w_a = open_box ? i_a : wrap_step(R.w0 * k0 + R.w1 * k1 + R.w2 * k2, st_a, n);
     const double t_a = (double(st_a > 0 ? i_a + 1 : i_a) - o_a) / d_a;
@@ -645,11 +630,7 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab
       (R.i0 < 0 || R.i0 >= n || R.i1 < 0 || R.i1 >= n || R.i2 < 0 || R.i2 >= n))
     return kEscaped;
   // absorber of the next cell, consumed by the next step
-  const int64_t cn = cell_index(R.w0, R.w1, R.w2, n);
-  if (MIXED)
-    R.a32 = A.a32[cn];
-  else
-    R.a64 = A.a64[cn];
+  R.a64 = A.a64[cell_index(R.w0, R.w1, R.w2, n)];
   return kGoOn;
 }
 
@@ -695,7 +676,7 @@ __device__ __forceinline__ void push_pending(unsigned long long* count, const Ra
 // to the compiler.
 template <bool MIXED, int CORR, bool PERIODIC, bool POLY>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu((MIXED && POLY && PERIODIC) ? 4 : 1, 8))) void k_march(
+__attribute__((amdgpu_waves_per_eu((MIXED && (PERIODIC || !POLY)) ? 4 : 1, 8))) void k_march(
     MarchArgs A) {
   using V = typename std::conditional<MIXED, float, double>::type;
   // per-wavefront deposit tables, reused for the budget reduction at the end
@@ -757,7 +738,7 @@ __attribute__((amdgpu_waves_per_eu((MIXED && POLY && PERIODIC) ? 4 : 1, 8))) voi
         const int64_t avail = pool_end - pool;
         const unsigned rank = lanes_below(idle);
         if (!busy && int64_t(rank) < avail) {
-          const Entry e = load_entry<MIXED && !POLY>(F, F.begin + pool + rank);
+          const Entry e = load_entry(F, F.begin + pool + rank);
           const int start = ray_init<MIXED, PERIODIC, POLY>(R, F, e);
           busy = start == kGoOn;
           if (!busy) acc.escaped += MIXED ? R.L * R.T : R.P;
@@ -777,7 +758,6 @@ __attribute__((amdgpu_waves_per_eu((MIXED && POLY && PERIODIC) ? 4 : 1, 8))) voi
         const double carried = MIXED ? R.L * R.T : R.P;
         acc.escaped += code == kEscaped ? carried : 0.0;
         acc.truncated += code == kTruncated ? carried : 0.0;
-        if (MIXED) acc.absorbed += R.L * R.absf;
       }
     }
     fill += __popcll(__ballot(inserted & 1)) + 2 * __popcll(__ballot(inserted & 2)) +
@@ -794,7 +774,7 @@ __attribute__((amdgpu_waves_per_eu((MIXED && POLY && PERIODIC) ? 4 : 1, 8))) voi
       p_src = R.src;
       p_pix = R.pix;
       p_s = R.s;
-      p_w = (MIXED && !POLY) ? R.T : R.tau;
+      p_w = R.tau;
     }
     if (__popcll(__ballot(pend)) >= 32) {
       ArgsK& F = fresh_args();
@@ -851,7 +831,7 @@ __global__ void k_prep(const double* __restrict__ n_H, const double* __restrict_
     if (!(nh >= 0.0) || isinf(nh) || !(xx >= 0.0 && xx <= 1.0)) ++bad;
     const double a = (1.0 - xx) * nh;
     const bool usable = nh >= n_th && a > 0.0;
-    if (a64) a64[c] = usable ? a : -a;
+    a64[c] = usable ? a : -a;
     if (a32) {
       float af = float(a);
       if (usable && af < FLT_MIN) af = FLT_MIN;
@@ -859,6 +839,32 @@ __global__ void k_prep(const double* __restrict__ n_H, const double* __restrict_
     }
   }
   if (bad) atomicAdd(&acc->invalid, bad);
+}
+
+// The threshold optical depth at which a spectrum's Phi reaches tau_max:
+// the smallest tau with Phi(tau) >= tau_max on the FP64 table, to the last
+// bit, by bisection of [0, hi] (Phi(0) = 0 < tau_max and Phi(hi) >= tau_max
+// at the table's end).  The march stops a ray once its threshold optical
+// depth reaches it, which is the photon-share cap F <= e^{-tau_max} taken on
+// an FP64 quantity that both precisions accumulate alike.  One thread.
+struct SpecTable {
+  int32_t spec_nint;
+  const SpecRec64* spec64;
+  const SpecRec32* spec32;
+};
+
+__global__ void k_spec_stop(SpecTable t, double tau_max, double hi, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double lo = 0.0;
+  for (int it = 0; it < 4096; ++it) {
+    const double mid = lo + 0.5 * (hi - lo);
+    if (!(mid > lo && mid < hi)) break;
+    if (spec_phi(t, mid) >= tau_max)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  *out = hi;
 }
 
 __global__ void k_fill_zero(double* p, int64_t count) {
@@ -913,12 +919,24 @@ int grid_for(int64_t items, int block, int cap) {
 
 }  // namespace
 
+hipError_t launch_prep_fields(const double* n_H, const double* x, double n_th, int64_t ncell,
+                              double* a64, float* a32, Accum* acc, int cus, hipStream_t s) {
+  hipLaunchKernelGGL(k_prep, dim3(grid_for(ncell, 256, cus * 16)), dim3(256), 0, s, n_H, x, n_th,
+                     ncell, a64, a32, acc);
+  return hipGetLastError();
+}
+
 hipError_t launch_prep(nrt_ctx* c) {
-  const int64_t ncell = c->lay.cells;
-  const bool mixed = c->desc.precision == NRT_MIXED;
-  hipLaunchKernelGGL(k_prep, dim3(grid_for(ncell, 256, c->cu_count * 16)), dim3(256), 0,
-                     c->stream, c->n_H, c->x, c->desc.n_th, ncell, mixed ? nullptr : c->a64,
-                     mixed ? c->a32 : nullptr, c->acc);
+  return launch_prep_fields(c->n_H, c->x, c->desc.n_th, c->lay.cells, c->a64,
+                            c->desc.precision == NRT_MIXED ? c->a32 : nullptr, c->acc,
+                            c->cu_count, c->stream);
+}
+
+hipError_t launch_spec_stop(const nrt_ctx* c, double* out) {
+  const SpecTable t{c->spec_nint, c->spec64, c->spec32};
+  // the table ends at an octave boundary: node tau 2^octaves - 1
+  const double hi = std::ldexp(1.0, c->spec_nint >> kSpecLog2Sub) - 1.0;
+  hipLaunchKernelGGL(k_spec_stop, dim3(1), dim3(64), 0, c->stream, t, c->desc.tau_max, hi, out);
   return hipGetLastError();
 }
 
@@ -970,19 +988,41 @@ hipError_t march_blocks_per_cu(const nrt_grid_desc& d, int* blocks) {
 }
 
 // persistent grid: as many blocks as stay resident, or fewer for small launches
-hipError_t launch_march(const nrt_ctx* c, const MarchArgs& args, int64_t rays, hipStream_t st) {
-  int per_cu = c->march_blocks_per_cu > 0 ? c->march_blocks_per_cu : 2;
-  if (c->tuning.blocks_per_cu > 0 && c->tuning.blocks_per_cu < per_cu)
-    per_cu = c->tuning.blocks_per_cu;
-  const int blocks = grid_for(rays, kBlock, c->cu_count * per_cu);
+hipError_t launch_march_on(const nrt_grid_desc& d, int cu_count, int resident_per_cu,
+                           const nrt_tuning& t, const MarchArgs& args, int64_t rays,
+                           hipStream_t st) {
+  int per_cu = resident_per_cu > 0 ? resident_per_cu : 2;
+  if (t.blocks_per_cu > 0 && t.blocks_per_cu < per_cu) per_cu = t.blocks_per_cu;
+  const int blocks = grid_for(rays, kBlock, cu_count * per_cu);
   MarchArgs a = args;
   // defaults from sweeps of the device-driven pass on the 128^3, 256^3 and
   // 512^3 workloads: runs of two wavefronts of rays halve the claims of
   // short-ray workloads without starving waves at the end of a level; a
   // refill once 16 lanes idle amortizes the ray set-up
-  a.claim = c->tuning.claim > 0 ? c->tuning.claim : 128;
-  a.refill_min = c->tuning.refill_min > 0 ? c->tuning.refill_min : 16;
-  hipLaunchKernelGGL(march_kernel(c->desc), dim3(blocks), dim3(kBlock), 0, st, a);
+  a.claim = t.claim > 0 ? t.claim : 128;
+  a.refill_min = t.refill_min > 0 ? t.refill_min : 16;
+  hipLaunchKernelGGL(march_kernel(d), dim3(blocks), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_march(const nrt_ctx* c, const MarchArgs& args, int64_t rays, hipStream_t st) {
+  return launch_march_on(c->desc, c->cu_count, c->march_blocks_per_cu, c->tuning, args, rays,
+                         st);
+}
+
+namespace {
+// l0[k] = ndot[k] / 12, the rate of a level-0 ray (a correctly rounded
+// division, as on the host)
+__global__ void k_source_rates(const double* ndot, int64_t m, double* l0) {
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < m;
+       k += int64_t(gridDim.x) * blockDim.x)
+    l0[k] = ndot[k] / 12.0;
+}
+}  // namespace
+
+hipError_t launch_source_rates(const double* ndot, int64_t m, double* l0, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_source_rates, dim3(grid_for(m, 256, 1024)), dim3(256), 0, s, ndot, m, l0);
   return hipGetLastError();
 }
 
