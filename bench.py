@@ -3,18 +3,23 @@
 A step is one full trace pass (nrt_trace_step: spawn, march, deposit,
 split, terminate, until no ray is left) over the workload's sources, with
 the grid, ionization field and source table already resident in HBM.  The
-default workload is the 128^3 lognormal field with 64 sources.  Both
-arithmetic paths are timed.  `value` is the mixed path's segments/s; the
-FP64 path is reported beside it.
+default workload is the largest: the 1024^3 late-reionization field with
+262 144 clustered sources, merged before the timed passes.  Both arithmetic
+paths are timed.  `value` is the mixed path's segments/s over exactly
+--steps passes after --warmup; the FP64 path is reported beside it, on as
+many passes as the run's time allows (at least one full pass, which also
+gives the mixed path's error against FP64).
 
 Prints one JSON line with the metric, the roofline of the march kernel
 (algorithmic bytes per launch over the average launch duration, from HIP
-events on the library's stream) and the oracle timed on the host cores on a
-bounded sample of the same workload.
+events on the library's stream), the measured copy bandwidth of the device,
+and the oracle timed on all host cores on a bounded sample of the same
+workload.
 """
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -24,9 +29,15 @@ sys.path.insert(0, ROOT)
 METRIC = "ray-segments/sec + ms per RT step, FP32-mixed vs FP64, % HBM roofline"
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per segment: absorber of the cell and of its neighbour,
-# read-modify-write of Gamma in both (FP64: 8+8+16+16; mixed: FP32 absorber
-# words, FP64 Gamma accumulators: 4+4+16+16)
-BYTES_PER_SEGMENT = {"fp64": 48.0, "mixed": 40.0}
+# read-modify-write of Gamma in both (FP64: 8+8+16+16; mixed: the cell's FP64
+# absorber word, which carries the optical depth of the decisions, the
+# neighbour's FP32 word, FP64 Gamma accumulators: 8+4+16+16)
+BYTES_PER_SEGMENT = {"fp64": 48.0, "mixed": 44.0}
+DEFAULT_WORKLOAD = "late-reion-1024-262144src"
+# wall-clock budget of a default run (the driver allows 600 s): the FP64 leg
+# and the oracle baseline shrink to fit what the timed mixed passes leave
+RUN_BUDGET_S = 480.0
+T_START = time.perf_counter()
 
 
 def log(*a):
@@ -99,10 +110,14 @@ def subset_indices(m, k, seed=11):
 
 
 def run_path(nrt, w, precision, steps, warmup, capacity, graph=0, sources=0, tune=False,
-             spectrum=(0, 0.0), tuned=None):
+             spectrum=(0, 0.0), tuned=None, deadline=None):
     """Time `steps` trace passes (after `warmup` untimed ones) of one
     arithmetic path.  Merging workloads merge first (timed on its own); with
-    `sources`, a seeded subset of the (merged) catalogue is traced."""
+    `sources`, a seeded subset of the (merged) catalogue is traced.  With a
+    `deadline` (perf_counter seconds), timed passes after the first stop once
+    another would end past it, and warm-up passes are skipped once one would.
+    Each timed pass is also bracketed by HIP events on the stream the library
+    uses (torch's current stream), whose median is reported."""
     import torch
     desc = nrt.make_desc(w.n, w.h_cm, periodic=w.periodic, n_min_ray=w.n_min_ray, l_max=w.l_max,
                          tau_max=w.tau_max, n_th=w.n_th, precision=precision,
@@ -133,29 +148,47 @@ def run_path(nrt, w, precision, steps, warmup, capacity, graph=0, sources=0, tun
         t = ctx.autotune(passes=1, gamma=gamma)
         tuning = dict(t)
         log(f"autotuned: {tuning}")
+    pass_s = None
     for i in range(warmup):
+        if deadline and pass_s and time.perf_counter() + pass_s > deadline:
+            log(f"  warm-up stopped after {i} passes (time budget)")
+            break
+        t0 = time.perf_counter()
         _, b = ctx.trace_step(gamma)
-        log(f"  warm-up pass {i + 1}/{warmup}: {b['segments']} segments")
+        pass_s = time.perf_counter() - t0
+        log(f"  warm-up pass {i + 1}/{warmup}: {b['segments']} segments, {pass_s:.2f} s")
     torch.cuda.synchronize()
-    segs, kernel_ms, launches = 0, 0.0, 0
+    segs, kernel_ms, launches, done = 0, 0.0, 0, 0
+    stream = torch.cuda.current_stream()
+    events = []
     t0 = time.perf_counter()
     for i in range(steps):
+        if deadline and done and time.perf_counter() + (time.perf_counter() - t0) / done > deadline:
+            log(f"  timed passes stopped after {done} (time budget)")
+            break
+        ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        ev[0].record(stream)
         _, b = ctx.trace_step(gamma)
+        ev[1].record(stream)
+        events.append(ev)
         avg, nl = ctx.last_kernel_time()
         kernel_ms += avg * nl
         launches += nl
         segs += b["segments"]
+        done += 1
         if steps > 1 and w.n >= 512:
             log(f"  pass {i + 1}/{steps}: {time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    ev_ms = sorted(a.elapsed_time(z) for a, z in events)
     graph = ctx.last_pass_was_graph()
     ctx.destroy()
-    return dict(wall_s=wall, steps=steps, ms_per_step=1e3 * wall / steps,
-                segments_per_step=segs // steps,
+    return dict(wall_s=wall, steps=done, ms_per_step=1e3 * wall / done,
+                ms_per_step_median_event=ev_ms[len(ev_ms) // 2],
+                segments_per_step=segs // done,
                 segments_per_s=segs / wall, kernel_ms_total=kernel_ms, launches=launches,
                 avg_launch_ms=kernel_ms / max(launches, 1), budget=b, graph=graph, gamma=gamma,
-                merge_ms=merge_ms, sources_traced=m_traced, tuning=tuning)
+                merge_ms=merge_ms, sources_traced=m_traced, tuning=tuning, warmup=warmup)
 
 
 def run_rt(nrt, w, precision, capacity, steps=0, dt_myr=0.0, conv_frac=0.0, spectrum=(0, 0.0)):
@@ -245,16 +278,18 @@ def corr_study(nrt, w, precision, capacity):
 def mixed_vs_fp64(mx, f64):
     """Error of the mixed result against the FP64 one: Gamma relative error
     where Gamma > 1e-6 max (max and 99.9th percentile), budget terms relative
-    to the emitted rate, and the count differences."""
+    to the emitted rate, and the count differences (zero: every decision is
+    FP64 and shared)."""
     import torch
     g, r = mx["gamma"], f64["gamma"]
     mask = r > 1e-6 * r.max()
     rel = (g[mask] / r[mask] - 1).abs()
-    k = max(1, int(0.999 * rel.numel()))
+    top = max(1, rel.numel() - int(0.999 * rel.numel()) + 1)  # the largest 0.1 %
+    p999 = torch.topk(rel, top, sorted=False).values.min()
     bm, bf = mx["budget"], f64["budget"]
     e = bf["emitted"]
     return {"gamma_max_rel": float(rel.max()),
-            "gamma_p999_rel": float(torch.kthvalue(rel.cpu(), k).values),
+            "gamma_p999_rel": float(p999),
             "budget_max_rel": max(abs(bm[t] - bf[t]) / e for t in ("absorbed", "escaped",
                                                                     "truncated")),
             "segments_rel": (bm["segments"] - bf["segments"]) / bf["segments"],
@@ -262,31 +297,45 @@ def mixed_vs_fp64(mx, f64):
             "splits_rel": (bm["splits"] - bf["splits"]) / max(bf["splits"], 1)}
 
 
-def roofline(path, res, counters=None):
+def roofline(path, res, counters=None, copy_gbs=None):
     """Per launch: the algorithmic bytes of the segments one march launch
     processes over the launch's duration (HIP events on the library's
     stream); averaged over the timed launches this is bytes per segment times
     segments over the summed launch time.  `traffic`: HBM bytes per launch
-    from the committed counter summary of the same kernel, else None."""
+    from the committed counter summary of the same kernel and workload, else
+    None; with it, `hbm_frac_measured` is that traffic over the average launch
+    against the peak (the share of HBM bandwidth the launch really draws).
+    `copy_GBs` is a timed device-to-device copy on the same device (the
+    streaming ceiling in practice)."""
     achieved = BYTES_PER_SEGMENT[path] * res["segments_per_s_kernel"] / 1e9
     traffic = None
     mode = "graph" if res.get("graph") else "host"
     if counters and counters.get(f"{path}_mode") == mode and \
             f"{path}_traffic_bytes_per_launch" in counters:
         traffic = float(counters[f"{path}_traffic_bytes_per_launch"])
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_march", "bytes_per_segment": BYTES_PER_SEGMENT[path],
-            "avg_launch_ms": round(res["avg_launch_ms"], 4), "launches": res["launches"],
-            "algorithmic_bytes_per_launch": round(
-                BYTES_PER_SEGMENT[path] * res["segments_per_step"] * res["steps"]
-                / max(res["launches"], 1), 1),
-            "mode": mode}
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "kernel": "k_march", "bytes_per_segment": BYTES_PER_SEGMENT[path],
+           "avg_launch_ms": round(res["avg_launch_ms"], 4), "launches": res["launches"],
+           "algorithmic_bytes_per_launch": round(
+               BYTES_PER_SEGMENT[path] * res["segments_per_step"] * res["steps"]
+               / max(res["launches"], 1), 1),
+           "mode": mode}
+    if traffic:
+        out["hbm_frac_measured"] = round(traffic / (res["avg_launch_ms"] * 1e-3) / 1e9
+                                         / HBM_PEAK_GBS, 4)
+    if copy_gbs:
+        out["copy_GBs"] = round(copy_gbs, 1)
+        out["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    return out
 
 
 KERNEL_SOURCES = ["paper_2512_12466_amd/csrc/trace.hip", "paper_2512_12466_amd/csrc/healpix.h",
                   "paper_2512_12466_amd/csrc/internal.h"]
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_march_counters_lognormal-128-64src.txt")
+
+
+def counters_file(workload):
+    return os.path.join(ROOT, "profiles", f"k_march_counters_{workload}.txt")
 
 
 def kernel_hash():
@@ -297,13 +346,15 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def read_counters():
-    """HBM bytes per march launch from the committed counter summary, or None
-    if the march kernel's sources changed since the counters were taken."""
-    if not os.path.exists(COUNTERS_FILE):
+def read_counters(workload):
+    """HBM bytes per march launch from the committed counter summary of a
+    workload, or None if there is none or the march kernel's sources changed
+    since the counters were taken."""
+    path = counters_file(workload)
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(COUNTERS_FILE):
+    for line in open(path):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
@@ -312,14 +363,15 @@ def read_counters():
     return kv
 
 
-def summarize_counters(d, out):
+def summarize_counters(d, out=None):
     """Summarize two rocprofv3 --pmc runs of `bench.py --calibrate-copy 1024`
     (FETCH_SIZE in fetch_counter_collection.csv, WRITE_SIZE in
     write_counter_collection.csv, each run's JSON line in fetch_bench.json /
     write_bench.json): each counter is scaled by what it reads for the
     calibration copies of known size, then averaged over the march launches
     of the run's last (timed) step, whose count and mode (host-driven or
-    graph replay) the JSON line gives."""
+    graph replay) the JSON line gives.  Written to `out`, by default the
+    counter summary of the workload the JSON line names."""
     import csv
     import collections
 
@@ -349,6 +401,9 @@ def summarize_counters(d, out):
             agg[key] = (sum(per[i] for i in ids), len(ids))
         return agg
     lf, lw = bench_line("fetch_bench.json"), bench_line("write_bench.json")
+    workload = json.loads([x for x in open(os.path.join(d, "fetch_bench.json"))
+                           if x.startswith("{")][-1])["config"].get("workload", DEFAULT_WORKLOAD)
+    out = out or counters_file(workload)
     # the chunking of a host-driven pass follows the order in which children
     # reach the queue, so the launch count may differ by one between runs
     assert {p: m for p, (_, m) in lf.items()} == {p: m for p, (_, m) in lw.items()}, (lf, lw)
@@ -359,8 +414,8 @@ def summarize_counters(d, out):
     lines = ["# HBM traffic of k_march from FETCH_SIZE / WRITE_SIZE counter runs",
              "# command (FETCH_SIZE; then WRITE_SIZE with -o write > write_bench.json): "
              "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o fetch -- "
-             "python3 bench.py --steps 1 --warmup 2 --no-cpu-baseline --calibrate-copy 1024 "
-             "> <dir>/fetch_bench.json",
+             f"python3 bench.py --workload {workload} --steps 1 --warmup 2 --no-cpu-baseline "
+             "--calibrate-copy 1024 > <dir>/fetch_bench.json",
              "# summarized with: python bench.py --summarize-counters <dir>",
              "# bytes per launch: counter KiB x 1024 / copy factor, averaged over the march "
              "launches of the timed step",
@@ -380,9 +435,38 @@ def summarize_counters(d, out):
     print("\n".join(lines))
 
 
-def cpu_baseline(w, sources, threads, spectrum=(0, 0.0)):
+def host_cpu():
+    """(nproc, the CPU share of this process, the CPU model)."""
+    model = platform.processor() or "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    share = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return os.cpu_count() or 1, share or 1, model
+
+
+# oracle baseline sample per workload: sources of the (unmerged) catalogue,
+# sized for 10-30 s of oracle work (the oracle keeps a private FP64 Gamma
+# per thread within 16 GB, so at 1024^3 it runs one thread, and a source of
+# the late-reionization field casts about 3e8 segments)
+CPU_SOURCES = {"lognormal-128-64src": 64, "lognormal-256-4096src-bubbles": 64,
+               "clustered-512-32768src": 64, "late-reion-1024-262144src": 1}
+
+
+def cpu_baseline(w, sources, spectrum=(0, 0.0)):
+    """The oracle as it stands, on a seeded subset of the workload's sources
+    over the full grid, on as many threads as this process's CPU share allows
+    (at most 16, the host share of one GPU)."""
     import oracle
     import workloads as W
+    nproc, share, model = host_cpu()
+    # the oracle's own caps: the CPU share, 16, the sources, 16 GB of Gamma
+    threads = max(1, min(16, share, len(w.ndot) if sources <= 0 else sources,
+                         int(16e9 / (8.0 * w.n ** 3))))
     s = W.subset(w, sources)
     p = oracle.make_params(w.n, w.h_cm, periodic=w.periodic, n_min_ray=w.n_min_ray,
                            l_max=w.l_max, tau_max=w.tau_max, n_th=w.n_th,
@@ -390,25 +474,53 @@ def cpu_baseline(w, sources, threads, spectrum=(0, 0.0)):
     t0 = time.perf_counter()
     _, b = oracle.trace(p, s.n_H, s.x, s.pos, s.ndot, nthreads=threads)
     dt = time.perf_counter() - t0
+    log(f"oracle baseline: {b['segments']} segments in {dt:.1f} s on {threads} threads")
     return {"value": round(b["segments"] / dt, 1), "unit": "ray-segments/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "nproc": nproc, "cpu_share": share, "cpu_model": model,
             "sample": (f"all {len(w.ndot)} sources" if len(s.ndot) == len(w.ndot) else
-                       f"{len(s.ndot)} of {len(w.ndot)} sources (seeded subset)")
-                      + f" of {w.name}, full grid, FP64, {b['segments']} segments in {dt:.1f} s"}
+                       f"{len(s.ndot)} of {len(w.ndot)} sources (seeded subset, unmerged)")
+                      + f" of {w.name}, full grid, FP64, {b['segments']} segments in {dt:.1f} s "
+                      "(absorber set-up included)"}
+
+
+def copy_bandwidth(gib=2, reps=5):
+    """Device-to-device copy of `gib` GiB, timed with HIP events: (read +
+    write bytes) / median time, in GB/s."""
+    import torch
+    src = torch.ones(gib << 27, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ms = []
+    for _ in range(reps):
+        a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        z.record()
+        z.synchronize()
+        ms.append(a.elapsed_time(z))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * (gib << 30) / (sorted(ms)[reps // 2] * 1e-3) / 1e9
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="lognormal-128-64src")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--capacity", type=int, default=0,
                     help="ray slots per HEALPix level queue (24 B each); default 2^25, "
                          "2^27 for the 1024^3 workload")
-    ap.add_argument("--paths", default="mixed,fp64")
-    ap.add_argument("--cpu-sources", type=int, default=64,
-                    help="sources the oracle baseline traces (64: the whole 128^3 pass)")
+    ap.add_argument("--paths", default="mixed,fp64",
+                    help="arithmetic paths; the first (mixed, if listed) is the headline")
+    ap.add_argument("--fp64-steps", type=int, default=0,
+                    help="timed passes of the second path (default: --steps, cut to the "
+                         "run's time budget, at least one)")
+    ap.add_argument("--budget-s", type=float, default=RUN_BUDGET_S,
+                    help="wall-clock budget that the second path's passes must fit")
+    ap.add_argument("--cpu-sources", type=int, default=0,
+                    help="sources the oracle baseline traces (default per workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=0, choices=(0, 1, 2),
                     help="0: replay the captured pass once eligible (default), 1: never, 2: always")
@@ -436,7 +548,7 @@ def main():
                          "traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.summarize_counters:
-        summarize_counters(args.summarize_counters, COUNTERS_FILE)
+        summarize_counters(args.summarize_counters)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path "
@@ -455,6 +567,9 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: 3 x {args.calibrate_copy} MiB")
         del src, dst
+    copy_gbs = None if args.calibrate_copy else copy_bandwidth()
+    if copy_gbs:
+        log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
     spectrum = parse_spectrum(args.spectrum)
     launch = (tuple(int(v) for v in args.launch.split(",")) if args.launch
               else launch_params(args.workload, spectrum[0]))
@@ -469,22 +584,33 @@ def main():
             p: corr_study(nrt, w, nrt.MIXED if p == "mixed" else nrt.FP64, args.capacity)
             for p in args.paths.split(",")}}), flush=True)
         return
+    paths = args.paths.split(",")
+    head = "mixed" if "mixed" in paths else paths[0]
+    paths = [head] + [p for p in paths if p != head]
     res = {}
-    for path in args.paths.split(","):
+    for path in paths:
         prec = nrt.MIXED if path == "mixed" else nrt.FP64
-        r = run_path(nrt, w, prec, args.steps, args.warmup, args.capacity, args.graph,
-                     args.sources, args.tune, spectrum, launch)
-        r["segments_per_s_kernel"] = r["segments_per_step"] * args.steps / (
+        if path == head:  # exactly --steps timed passes after --warmup
+            steps, warmup, deadline = args.steps, args.warmup, None
+        else:  # as many as the budget leaves (at least one), for the comparison
+            steps = args.fp64_steps or args.steps
+            warmup, deadline = min(args.warmup, 2), T_START + args.budget_s
+        r = run_path(nrt, w, prec, steps, warmup, args.capacity, args.graph, args.sources,
+                     args.tune, spectrum, launch, deadline=deadline)
+        r["segments_per_s_kernel"] = r["segments_per_step"] * r["steps"] / (
             r["kernel_ms_total"] / 1e3)
         res[path] = r
-        log(f"[{path}] {r['ms_per_step']:.2f} ms/step, {r['segments_per_step']} segments, "
+        log(f"[{path}] {r['ms_per_step']:.2f} ms/step over {r['steps']} passes, "
+            f"{r['segments_per_step']} segments, "
             f"{r['segments_per_s'] / 1e9:.3f} Gseg/s wall, "
             f"{r['segments_per_s_kernel'] / 1e9:.3f} Gseg/s in march kernels "
-            f"({r['launches'] // args.steps} launches/step, "
-            f"{'graph replay' if r['graph'] else 'host-driven'})")
+            f"({r['launches'] // r['steps']} launches/step, "
+            f"{'graph replay' if r['graph'] else 'host-driven'}), "
+            f"{time.perf_counter() - T_START:.0f} s into the run")
     err = mixed_vs_fp64(res["mixed"], res["fp64"]) if {"mixed", "fp64"} <= set(res) else None
     for r in res.values():
         r.pop("gamma")
+    torch.cuda.empty_cache()
     rt = None
     if "steps" in w.extra or args.rt_steps:  # radiation steps with the chemistry iteration
         rt = {path: run_rt(nrt, w, nrt.MIXED if path == "mixed" else nrt.FP64, args.capacity,
@@ -493,22 +619,21 @@ def main():
         for path, v in rt.items():
             log(f"[{path}] {v['ms_per_rt_step']:.2f} ms per RT step, iterations {v['iterations']}"
                 + (f", r/r_closed-form {v['r_ratio']:.4f}" if "r_ratio" in v else ""))
-    head = "mixed" if "mixed" in res else next(iter(res))
     h = res[head]
-    # the committed counter summary covers the default workload's monochromatic pass
-    counters = (read_counters() if args.workload == "lognormal-128-64src" and spectrum[0] == 0
-                and not args.sources else None)
+    # committed counter summaries cover monochromatic passes of whole catalogues
+    counters = read_counters(w.name) if spectrum[0] == 0 and not args.sources else None
     out = {
         "metric": METRIC, "value": round(h["segments_per_s"], 1), "unit": "ray-segments/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "n_gpus": 1, "steps": h["steps"], "warmup": args.warmup,
         "ms_per_step": round(h["ms_per_step"], 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if head == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "sources": int(len(w.ndot)),
                    "periodic": bool(w.periodic), "n_min_ray": w.n_min_ray, "l_max": w.l_max,
                    "tau_max": w.tau_max, "path": head, "decisions": "f64",
-                   "graph": bool(h["graph"]), "spectrum": spectrum_config(spectrum)},
-        "roofline": roofline(head, h, counters),
+                   "graph": bool(h["graph"]), "spectrum": spectrum_config(spectrum),
+                   "ms_per_step_median_event": round(h["ms_per_step_median_event"], 3)},
+        "roofline": roofline(head, h, counters, copy_gbs),
     }
     out["config"]["per_pass"] = {k: h["budget"][k] for k in ("segments", "rays", "splits")}
     if w.merge or args.sources:
@@ -525,11 +650,14 @@ def main():
             continue
         out[f"{path}_path"] = {"value": round(r["segments_per_s"], 1), "unit": "ray-segments/s",
                                "ms_per_step": round(r["ms_per_step"], 3),
+                               "ms_per_step_median_event": round(r["ms_per_step_median_event"], 3),
+                               "steps": r["steps"], "warmup": r["warmup"],
                                "dtype": "f64" if path == "fp64" else "f32",
-                               "roofline": roofline(path, r, counters)}
+                               "roofline": roofline(path, r, counters, copy_gbs)}
     if not args.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sources, threads, spectrum)
+        k = args.cpu_sources or CPU_SOURCES.get(w.name, 64)
+        out["cpu_baseline"] = cpu_baseline(w, k, spectrum)
+    log(f"done in {time.perf_counter() - T_START:.0f} s")
     print(json.dumps(out), flush=True)
 
 

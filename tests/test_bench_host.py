@@ -37,15 +37,19 @@ def test_roofline_arithmetic():
     res = dict(segments_per_s_kernel=5e10, avg_launch_ms=2.0, launches=20,
                segments_per_step=10 ** 9, steps=2, graph=True)
     r = bench.roofline("mixed", res, None)
-    assert r["achieved"] == pytest.approx(40 * 5e10 / 1e9)  # 40 B per mixed segment
-    assert r["frac"] == pytest.approx(2000.0 / 8000.0)
-    assert r["algorithmic_bytes_per_launch"] == pytest.approx(40 * 1e9 * 2 / 20)
+    assert r["achieved"] == pytest.approx(44 * 5e10 / 1e9)  # 44 B per mixed segment
+    assert r["frac"] == pytest.approx(2200.0 / 8000.0)
+    assert r["algorithmic_bytes_per_launch"] == pytest.approx(44 * 1e9 * 2 / 20)
     assert r["traffic"] is None and r["mode"] == "graph" and r["bound"] == "hbm"
     f = bench.roofline("fp64", dict(res, graph=False), None)
     assert f["achieved"] == pytest.approx(48 * 5e10 / 1e9) and f["mode"] == "host"
     # the summary's traffic is used only for the launch mode it was measured in
-    c = {"mixed_mode": "graph", "mixed_traffic_bytes_per_launch": "123.5"}
-    assert bench.roofline("mixed", res, c)["traffic"] == 123.5
+    c = {"mixed_mode": "graph", "mixed_traffic_bytes_per_launch": "4e9"}
+    rc = bench.roofline("mixed", res, c, copy_gbs=5000.0)
+    assert rc["traffic"] == 4e9
+    # measured traffic over the launch time against the peak: 4 GB / 2 ms
+    assert rc["hbm_frac_measured"] == pytest.approx(2000.0 / 8000.0)
+    assert rc["copy_GBs"] == 5000.0 and rc["frac_of_copy"] == pytest.approx(2200.0 / 5000.0)
     assert bench.roofline("mixed", dict(res, graph=False), c)["traffic"] is None
 
 
@@ -59,7 +63,7 @@ def _write_run(d, tag, copy_kib, march_kib, launches):
     for i, v in enumerate(march_kib):
         rows.append(f"{100 + i},\"void nrt::k_march<true, 2, true, false>(nrt::MarchArgs)\",X,{v}")
     open(os.path.join(d, f"{tag}_counter_collection.csv"), "w").write("\n".join(rows) + "\n")
-    line = {"steps": 1, "config": {"path": "mixed"},
+    line = {"steps": 1, "config": {"path": "mixed", "workload": "lognormal-128-64src"},
             "roofline": {"launches": launches, "mode": "graph"}}
     open(os.path.join(d, f"{tag}_bench.json"), "w").write("log line\n" + json.dumps(line) + "\n")
 
@@ -72,8 +76,9 @@ def test_counter_summary_and_staleness(tmp_path, monkeypatch):
     # two warm-up dispatches, then three timed ones
     _write_run(tmp_path, "fetch", fetch_copy_kib, [9e9, 9e9, 100.0, 200.0, 300.0], 3)
     _write_run(tmp_path, "write", write_copy_kib, [7e9, 50.0, 60.0, 70.0], 3)
-    out = tmp_path / "summary.txt"
-    bench.summarize_counters(str(tmp_path), str(out))
+    out = tmp_path / "k_march_counters_lognormal-128-64src.txt"
+    monkeypatch.setattr(bench, "counters_file", lambda w: str(tmp_path / f"k_march_counters_{w}.txt"))
+    bench.summarize_counters(str(tmp_path))
     kv = dict(l.split(" = ", 1) for l in out.read_text().splitlines() if " = " in l)
     assert float(kv["copy_factor_fetch"]) == pytest.approx(0.5)
     assert float(kv["copy_factor_write"]) == pytest.approx(1.0)
@@ -84,11 +89,11 @@ def test_counter_summary_and_staleness(tmp_path, monkeypatch):
     assert float(kv["mixed_traffic_bytes_per_launch"]) == pytest.approx(fetch + write, rel=1e-6)
     assert kv["mixed_mode"] == "graph" and kv["kernel_sha"] == bench.kernel_hash()
     # a summary is used only while the march kernel's sources are unchanged
-    monkeypatch.setattr(bench, "COUNTERS_FILE", str(out))
-    assert float(bench.read_counters()["mixed_traffic_bytes_per_launch"]) == pytest.approx(
-        fetch + write, rel=1e-6)
+    assert float(bench.read_counters("lognormal-128-64src")["mixed_traffic_bytes_per_launch"]) \
+        == pytest.approx(fetch + write, rel=1e-6)
+    assert bench.read_counters("clustered-512-32768src") is None  # no summary for it
     monkeypatch.setattr(bench, "kernel_hash", lambda: "0" * 16)
-    assert bench.read_counters() is None
+    assert bench.read_counters("lognormal-128-64src") is None
 
 
 def test_more_than_one_gpu_exits():
