@@ -24,5 +24,20 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+SANITIZERS = {"address": "address,undefined", "thread": "thread"}
+
+
+def build_sanitized(kind: str, out: str) -> str:
+    """The oracle with sanitize_main.c as a host executable built with gcc
+    under AddressSanitizer + UndefinedBehaviorSanitizer ("address") or
+    ThreadSanitizer ("thread")."""
+    cmd = ["gcc", "-std=c99", "-D_GNU_SOURCE", "-O1", "-g", "-fno-omit-frame-pointer",
+           "-ffp-contract=off", "-fno-fast-math", f"-fsanitize={SANITIZERS[kind]}",
+           "-fno-sanitize-recover=all", "-pthread", "-I" + HERE, "-o", out]
+    cmd += [os.path.join(HERE, s) for s in SOURCES + ["sanitize_main.c"]] + ["-lm"]
+    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    return out
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
