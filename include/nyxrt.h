@@ -236,9 +236,11 @@ nrt_status nrt_trace_rays_debug(nrt_ctx* ctx, int64_t k, const double* origin, c
                                 const int32_t* level, const double* L, double* gamma_out,
                                 nrt_budget* budget);
 
-/* HEALPix nested pixel-centre directions computed by the device code:
-   out host 3*count doubles for pixels first .. first+count-1 of `level`.
-   Used to check the device pixelisation. */
+/* HEALPix nested pixel-centre directions as the march uses them: out host
+   3*count doubles for pixels first .. first+count-1 of `level`.  Levels up
+   to min(l_max, 11) come from the context's direction table, which
+   nrt_init_grid computes on the host with the C library's cos and sin;
+   deeper levels are computed by the march's device function. */
 nrt_status nrt_healpix_dirs(nrt_ctx* ctx, int32_t level, int64_t first, int64_t count,
                             double* out);
 

@@ -5,11 +5,14 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <thread>
 
+#include "healpix.h"
 #include "internal.h"
 
 using nrt::Accum;
 using nrt::Layout;
+using nrt::RtState;
 using nrt::MarchArgs;
 using nrt::RayQueue;
 
@@ -239,13 +242,15 @@ nrt_status chunked_pass(nrt_ctx* c, double* gamma, nrt_budget* out) {
 // ray count from the accumulator block (written by the previous level), so
 // the whole pass runs without a host round trip.  Needs every level to fit
 // its queue; a launch that cannot store a split sets the overflow flag.
-hipError_t enqueue_device_pass(nrt_ctx* c, hipStream_t st, double* gamma) {
-  hipError_t e = nrt::launch_zero(gamma, c->lay.cells, c->cu_count, st);
-  if (e == hipSuccess) e = nrt::launch_zero_accum(c->acc, st);
+hipError_t enqueue_device_pass(nrt_ctx* c, hipStream_t st, double* gamma,
+                               const unsigned long long* skip = nullptr) {
+  hipError_t e = nrt::launch_zero(gamma, c->lay.cells, c->cu_count, st, skip);
+  if (e == hipSuccess) e = nrt::launch_zero_accum(c->acc, st, skip);
   const int64_t m = int64_t(c->h_ndot.size());
   const int64_t cap = c->lay.capacity;
   for (int level = 0; level <= c->desc.l_max && e == hipSuccess; ++level) {
     MarchArgs a = base_args(c, gamma);
+    a.skip = skip;
     a.level = level;
     a.spawn = level == 0 ? 1 : 0;
     a.begin = 0;
@@ -365,6 +370,38 @@ nrt_status trace_pass(nrt_ctx* c, double* gamma, nrt_budget* out) {
   return NRT_OK;
 }
 
+// The direction table of levels 0..c->lay.dir_levels, computed on the host
+// with the C library's cos and sin (the same calls, on the same operations,
+// as a host implementation of the pixelisation makes) and copied once.
+nrt_status fill_direction_table(nrt_ctx* c) {
+  const int64_t total = nrt::dir_table_offset(c->lay.dir_levels + 1);
+  std::vector<double> tab;
+  try {
+    tab.resize(size_t(total) * 3);
+  } catch (const std::bad_alloc&) {
+    return fail(c, NRT_ERR_NOMEM, "host memory for the direction table");
+  }
+  const int nt = int(std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+  auto work = [&](int t) {
+    for (int l = 0; l <= c->lay.dir_levels; ++l) {
+      const int64_t first = nrt::dir_table_offset(l), npix = 12 * (int64_t(1) << (2 * l));
+      const int64_t lo = npix * t / nt, hi = npix * (t + 1) / nt;
+      for (int64_t p = lo; p < hi; ++p) {
+        double* d = tab.data() + 3 * (first + p);
+        nrt::healpix_dir(l, uint32_t(p), d[0], d[1], d[2]);
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; ++t) th.emplace_back(work, t);
+  work(0);
+  for (auto& x : th) x.join();
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->dirs, tab.data(), tab.size() * sizeof(double),
+                                hipMemcpyHostToDevice, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return NRT_OK;
+}
+
 nrt_status prep_absorber(nrt_ctx* c, const double* x_field) {
   const double* keep = c->x;
   c->x = const_cast<double*>(x_field);
@@ -377,6 +414,114 @@ nrt_status prep_absorber(nrt_ctx* c, const double* x_field) {
   if (c->h_acc->invalid)
     return fail(c, NRT_ERR_ARG, std::to_string(c->h_acc->invalid) +
                                     " cells with n_H < 0, non-finite n_H or x outside [0,1]");
+  return NRT_OK;
+}
+
+// Whether the radiation step's passes can replay a captured graph: the
+// device-driven pass fits every level (shown by an earlier pass) and the
+// tuning allows graphs.
+bool rt_graph_usable(const nrt_ctx* c) {
+  return !c->h_ndot.empty() && c->tuning.graph != 1 && (c->tuning.graph == 2 || c->graph_eligible);
+}
+
+// Capture one pass of a radiation step on the private stream: the absorber
+// from x_avg, the device-driven trace into gamma, the chemistry into x_avg
+// and x_new, and the convergence check, every kernel skipped once the check
+// has stopped the iteration.  Clears are kernels (no memset nodes).
+nrt_status capture_rt_graph(nrt_ctx* c, double dt, double alpha, double tol,
+                            unsigned long long threshold, int64_t max_iter, double* gamma,
+                            double* x_avg, double* x_new) {
+  if (c->rt_exec) {
+    HIP_OR_FAIL(c, hipGraphExecDestroy(c->rt_exec));
+    c->rt_exec = nullptr;
+  }
+  if (!c->capture_stream)
+    HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+  const unsigned long long* skip = &c->rt->done;
+  HIP_OR_FAIL(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+  hipStream_t s = c->capture_stream;
+  // the accumulators first: the absorber kernel counts invalid cells there
+  hipError_t e = nrt::launch_zero_accum(c->acc, s, skip);
+  if (e == hipSuccess) e = nrt::launch_prep_from(c, x_avg, skip, s);
+  if (e == hipSuccess) e = enqueue_device_pass(c, s, gamma, skip);
+  if (e == hipSuccess) e = nrt::launch_chem(c, gamma, dt, alpha, tol, x_avg, x_new, s, skip);
+  if (e == hipSuccess) e = nrt::launch_rt_check(c->acc, c->rt, threshold, max_iter, s);
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(s, &g);
+  if (e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_fail(c, e, "capture of a radiation-step pass");
+  }
+  if (e2 != hipSuccess) return hip_fail(c, e2, "hipStreamEndCapture");
+  const hipError_t e3 = hipGraphInstantiate(&c->rt_exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e3 != hipSuccess) {
+    c->rt_exec = nullptr;
+    return hip_fail(c, e3, "hipGraphInstantiate");
+  }
+  c->rt_key[0] = dt;
+  c->rt_key[1] = alpha;
+  c->rt_key[2] = tol;
+  c->rt_key[3] = double(threshold);
+  c->rt_max_iter = max_iter;
+  c->rt_gamma = gamma;
+  c->rt_sources = int64_t(c->h_ndot.size());
+  c->rt_tuning = c->tuning;
+  return NRT_OK;
+}
+
+// Replay the captured radiation-step pass until its check stops the
+// iteration, starting after `done_iters` host-driven passes: batches of 4
+// replays, one readback of the step state per batch.  The replays after the
+// stop return at once.  NRT_ERR_OVERFLOW if a level outgrew its queue.
+nrt_status rt_replay(nrt_ctx* c, double dt, double alpha, double tol, unsigned long long threshold,
+                     int32_t max_iter, int32_t done_iters, double* gamma, double* x_avg,
+                     double* x_new, nrt_budget* out, int32_t* iters) {
+  nrt_status st = upload_sources(c);
+  if (st) return st;
+  const int64_t left = int64_t(max_iter) - done_iters;
+  if (!c->rt_exec || c->rt_key[0] != dt || c->rt_key[1] != alpha || c->rt_key[2] != tol ||
+      c->rt_key[3] != double(threshold) || c->rt_max_iter != left || c->rt_gamma != gamma ||
+      c->rt_sources != int64_t(c->h_ndot.size()) ||
+      std::memcmp(&c->rt_tuning, &c->tuning, sizeof(nrt_tuning)) != 0) {
+    st = capture_rt_graph(c, dt, alpha, tol, threshold, left, gamma, x_avg, x_new);
+    if (st) return st;
+  }
+  HIP_OR_FAIL(c, nrt::launch_rt_reset(c->rt, c->stream));
+  RtState h;
+  for (;;) {
+    for (int r = 0; r < 4; ++r) HIP_OR_FAIL(c, hipGraphLaunch(c->rt_exec, c->stream));
+    HIP_OR_FAIL(c, hipMemcpyAsync(&c->h_acc->out_count[0], c->rt, sizeof(RtState),
+                                  hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    std::memcpy(&h, &c->h_acc->out_count[0], sizeof(RtState));
+    if (h.done) break;
+  }
+  if (h.overflow) return fail(c, NRT_ERR_OVERFLOW, "a level did not fit its queue");
+  if (h.invalid) return fail(c, NRT_ERR_INTERNAL, "the iterated ionized fraction left [0, 1]");
+  *iters = done_iters + int32_t(h.iters);
+  c->last_pass_graph = 1;
+  c->launches = 0;  // not timed
+  c->march_ms = 0.0;
+  // the budget of the last pass is still in the accumulators
+  st = sync_read_accum(c);
+  if (st) return st;
+  const Accum& a = *c->h_acc;
+  nrt_budget b;
+  std::memset(&b, 0, sizeof(b));
+  for (double v : c->h_ndot) b.emitted += v;
+  b.absorbed = a.absorbed;
+  b.escaped = a.escaped;
+  b.truncated = a.truncated;
+  b.segments = a.segments;
+  const int64_t m = int64_t(c->h_ndot.size());
+  for (int l = 0; l <= c->desc.l_max; ++l) {
+    const uint64_t k = l == 0 ? uint64_t(12 * m) : uint64_t(a.out_count[l]);
+    b.rays_per_level[l] = k;
+    b.rays += k;
+    if (l > 0) b.splits += k / 4;
+  }
+  if (out) *out = b;
   return NRT_OK;
 }
 
@@ -445,6 +590,8 @@ Layout plan_layout(const nrt_grid_desc& d, int64_t max_sources, int64_t capacity
   off += per_level * size_t(L.levels);
   L.accum = off;
   off = align256(off + sizeof(Accum));
+  L.rt = off;
+  off = align256(off + sizeof(RtState));
   L.dir_levels = std::min(d.l_max, nrt::kDirTableMaxLevel);
   L.dirs = off;
   off = align256(off + size_t(nrt::dir_table_offset(L.dir_levels + 1)) * 24);
@@ -555,6 +702,7 @@ nrt_status nrt_init_grid(nrt_ctx** out, const nrt_grid_desc* desc, const double*
     q += align256(cap * 8);
   }
   c->acc = reinterpret_cast<Accum*>(c->ws + L.accum);
+  c->rt = reinterpret_cast<nrt::RtState*>(c->ws + L.rt);
   c->scratch = c->ws + L.scratch;
   c->scratch_bytes = L.total - L.scratch;
   c->sources_dirty = true;
@@ -570,10 +718,8 @@ nrt_status nrt_init_grid(nrt_ctx** out, const nrt_grid_desc* desc, const double*
   if (e != hipSuccess) return bail(hip_fail(c, e, "field copy"));
   st = prep_absorber(c, c->x);
   if (st) return bail(st);
-  for (int l = 0; l <= L.dir_levels && e == hipSuccess; ++l)
-    e = nrt::launch_healpix(l, 0, 12 * (int64_t(1) << (2 * l)), c->dirs + 3 * nrt::dir_table_offset(l),
-                            c->stream);
-  if (e != hipSuccess) return bail(hip_fail(c, e, "direction table"));
+  st = fill_direction_table(c);
+  if (st) return bail(st);
   if (desc->spectrum != NRT_SPEC_MONO) {
     st = nrt::build_spectrum_table(c);
     if (st) return bail(st);
@@ -767,8 +913,14 @@ nrt_status nrt_healpix_dirs(nrt_ctx* c, int32_t level, int64_t first, int64_t co
     return fail(c, NRT_ERR_ARG, "bad HEALPix range");
   if (size_t(count) * 24 > c->scratch_bytes) return fail(c, NRT_ERR_NOMEM, "range too large");
   if (count == 0) return NRT_OK;
-  double* d = reinterpret_cast<double*>(c->scratch);
-  HIP_OR_FAIL(c, nrt::launch_healpix(level, first, count, d, c->stream));
+  // levels in the context's table are read from it (the march's values);
+  // deeper levels are computed by the march's device function
+  const double* d = reinterpret_cast<double*>(c->scratch);
+  if (level <= c->lay.dir_levels)
+    d = c->dirs + 3 * (nrt::dir_table_offset(level) + first);
+  else
+    HIP_OR_FAIL(c, nrt::launch_healpix(level, first, count, reinterpret_cast<double*>(c->scratch),
+                                       c->stream));
   HIP_OR_FAIL(c, hipMemcpyAsync(out, d, size_t(count) * 24, hipMemcpyDeviceToHost, c->stream));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   return NRT_OK;
@@ -782,21 +934,44 @@ nrt_status nrt_rt_step(nrt_ctx* c, double dt_s, double alpha, double tol, double
     return fail(c, NRT_ERR_ARG, "bad rt_step arguments");
   double* x_avg = reinterpret_cast<double*>(c->scratch);
   double* x_new = x_avg + c->lay.cells;
-  HIP_OR_FAIL(c, nrt::launch_copy(c, c->x, x_avg));
-  int32_t it = 1;
-  nrt_status st = NRT_OK;
-  for (;; ++it) {
+  // stop once at most this many cells changed x_avg by tol or more
+  const unsigned long long threshold =
+      (unsigned long long)std::floor(conv_frac * double(c->lay.cells));
+  // one host-driven pass: absorber from x_avg, trace, chemistry, readback;
+  // true when the iteration stops after it
+  int32_t it = 0;
+  auto host_pass = [&](nrt_status& st) {
+    ++it;
     st = prep_absorber(c, x_avg);
-    if (st) break;
-    st = trace_pass(c, gamma_out, budget);
-    if (st) break;
-    HIP_OR_FAIL(c, hipMemsetAsync(&c->acc->chem_changed, 0, sizeof(unsigned long long),
-                                  c->stream));
-    HIP_OR_FAIL(c, nrt::launch_chem(c, gamma_out, dt_s, alpha, tol, x_avg, x_new));
-    st = sync_read_accum(c);
-    if (st) break;
-    const double changed = double(c->h_acc->chem_changed);
-    if (changed <= conv_frac * double(c->lay.cells) || it >= max_iter) break;
+    if (!st) st = trace_pass(c, gamma_out, budget);
+    if (!st) {
+      hipError_t e = hipMemsetAsync(&c->acc->chem_changed, 0, sizeof(unsigned long long),
+                                    c->stream);
+      if (e == hipSuccess)
+        e = nrt::launch_chem(c, gamma_out, dt_s, alpha, tol, x_avg, x_new, c->stream);
+      st = e == hipSuccess ? sync_read_accum(c) : hip_fail(c, e, "chemistry");
+    }
+    return st || c->h_acc->chem_changed <= threshold || it >= max_iter;
+  };
+  nrt_status st = NRT_OK;
+  HIP_OR_FAIL(c, nrt::launch_copy(c, c->x, x_avg));
+  // the first pass, and every pass while the levels do not fit the queues,
+  // is host-driven; then the captured pass (absorber, trace, chemistry and
+  // the convergence check on the device) is replayed with one readback per
+  // batch of replays
+  bool done = host_pass(st);
+  while (!done && !rt_graph_usable(c)) done = host_pass(st);
+  if (!done) {
+    st = rt_replay(c, dt_s, alpha, tol, threshold, max_iter, it, gamma_out, x_avg, x_new, budget,
+                   &it);
+    if (st == NRT_ERR_OVERFLOW) {  // a level outgrew its queue: redo the step host-driven
+      c->graph_eligible = false;
+      HIP_OR_FAIL(c, nrt::launch_copy(c, c->x, x_avg));
+      it = 0;
+      st = NRT_OK;
+      while (!host_pass(st)) {
+      }
+    }
   }
   if (st) {
     prep_absorber(c, c->x);
@@ -912,6 +1087,7 @@ nrt_status nrt_destroy(nrt_ctx* c) {
   if (!c) return NRT_OK;
   (void)hipStreamSynchronize(c->stream);
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->rt_exec) (void)hipGraphExecDestroy(c->rt_exec);
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   if (c->h_acc) (void)hipHostFree(c->h_acc);

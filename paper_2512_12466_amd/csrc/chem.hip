@@ -15,7 +15,8 @@ namespace {
 __global__ void k_chem(const double* __restrict__ gamma, const double* __restrict__ n_H,
                        const double* __restrict__ x0, double dt, double alpha, double tol,
                        int64_t ncell, double* x_avg, double* x_new,
-                       unsigned long long* changed) {
+                       unsigned long long* changed, const unsigned long long* skip) {
+  if (skip && *skip) return;
   unsigned long long local = 0;
   for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < ncell;
        c += int64_t(gridDim.x) * blockDim.x) {
@@ -57,11 +58,12 @@ __global__ void k_copy(const double* __restrict__ src, double* dst, int64_t coun
 }  // namespace
 
 hipError_t launch_chem(const nrt_ctx* c, const double* gamma, double dt, double alpha, double tol,
-                       double* x_avg, double* x_new) {
+                       double* x_avg, double* x_new, hipStream_t s,
+                       const unsigned long long* skip) {
   int64_t blocks = (c->lay.cells + 255) / 256;
   if (blocks > int64_t(c->cu_count) * 16) blocks = int64_t(c->cu_count) * 16;
-  hipLaunchKernelGGL(k_chem, dim3(unsigned(blocks)), dim3(256), 0, c->stream, gamma, c->n_H,
-                     c->x, dt, alpha, tol, c->lay.cells, x_avg, x_new, &c->acc->chem_changed);
+  hipLaunchKernelGGL(k_chem, dim3(unsigned(blocks)), dim3(256), 0, s, gamma, c->n_H, c->x, dt,
+                     alpha, tol, c->lay.cells, x_avg, x_new, &c->acc->chem_changed, skip);
   return hipGetLastError();
 }
 

@@ -1,6 +1,8 @@
-// Device-side HEALPix nested pixel centres (Gorski et al. 2005), the
-// pixelisation along which the paper's rays split (Sec. "Adaptive ray
-// tracing", Fig. raysplit).
+// HEALPix nested pixel centres (Gorski et al. 2005), the pixelisation along
+// which the paper's rays split (Sec. "Adaptive ray tracing", Fig. raysplit).
+// The same function runs on the host, where the context fills its direction
+// table with the C library's cos and sin, and in the march for levels past
+// the table, with the device's.
 //
 // pix = face * Ns^2 + ipf with the in-face coordinates interleaved in ipf
 // (ix on even bits, iy on odd bits); ring jr = (face/4 + 2) Ns - ix - iy - 1;
@@ -17,7 +19,7 @@
 
 namespace nrt {
 
-__device__ __forceinline__ uint32_t hp_compact(uint32_t v) {
+__host__ __device__ inline uint32_t hp_compact(uint32_t v) {
   v &= 0x55555555u;
   v = (v | (v >> 1)) & 0x33333333u;
   v = (v | (v >> 2)) & 0x0F0F0F0Fu;
@@ -27,7 +29,8 @@ __device__ __forceinline__ uint32_t hp_compact(uint32_t v) {
 }
 
 // level <= 14, pix < 12 * 4^level: every integer below fits 32 bits
-__device__ inline void healpix_dir(int level, uint32_t pix, double& dx, double& dy, double& dz) {
+__host__ __device__ inline void healpix_dir(int level, uint32_t pix, double& dx, double& dy,
+                                            double& dz) {
   const int ns = 1 << level;
   const uint32_t face = pix >> (2 * level);
   const uint32_t ipf = pix - (face << (2 * level));

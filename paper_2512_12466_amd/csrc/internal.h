@@ -63,7 +63,21 @@ struct Accum {
   unsigned long long claim_lv[kMaxLevel + 2];  // claim counters of a device-driven pass
 };
 
+// State of a radiation step's Gamma <-> x iteration when its passes replay
+// a captured graph: written by k_rt_check at the end of every pass, read by
+// the host once per batch of replays.  Once `done` is set, every kernel of a
+// later replay returns at once.
+struct RtState {
+  unsigned long long done;      // 1 once the iteration has stopped
+  unsigned long long iters;     // passes done
+  unsigned long long changed;   // cells whose x_avg moved by tol or more (last pass)
+  unsigned long long overflow;  // a level of a pass did not fit its queue
+  unsigned long long invalid;   // cells of x_avg outside [0, 1]
+  unsigned long long pad[3];
+};
+
 struct MarchArgs {
+  const unsigned long long* skip;  // nonzero *skip: return at once (replays after a stop)
   // grid
   int32_t n, periodic, corr, l_max;
   int32_t level;     // HEALPix level of every input ray (-1: injected rays)
@@ -120,7 +134,7 @@ __host__ __device__ inline int64_t dir_table_offset(int level) {
 }
 
 struct Layout {
-  size_t n_H, x, a, srcpos, srcl0, srcaux, queues, accum, dirs, spec, scratch, total;
+  size_t n_H, x, a, srcpos, srcl0, srcaux, queues, accum, rt, dirs, spec, scratch, total;
   int64_t cells, max_sources, capacity;
   int levels;      // number of level queues (levels 1..l_max)
   int dir_levels;  // direction table covers levels 0..dir_levels
@@ -154,6 +168,13 @@ struct nrt_ctx {
   int64_t graph_sources;    // source count the graph was captured for
   nrt_tuning graph_tuning;  // launch parameters it was captured with
   bool graph_eligible;      // a previous pass fit every level in one queue
+  // captured pass of a radiation step (absorber, trace, chemistry, check)
+  hipGraphExec_t rt_exec;
+  double rt_key[4];         // dt, alpha, tol, change threshold it was captured with
+  int64_t rt_max_iter;
+  double* rt_gamma;
+  int64_t rt_sources;
+  nrt_tuning rt_tuning;
   int last_pass_graph;      // 1 if the last pass replayed the graph
   hipStream_t stream;
   char* ws;
@@ -172,6 +193,7 @@ struct nrt_ctx {
   double* src_l0;
   nrt::RayQueue queue[nrt::kMaxLevel + 1];
   nrt::Accum* acc;
+  nrt::RtState* rt;
   char* scratch;
   size_t scratch_bytes;
   // host mirror of the source table
@@ -193,6 +215,9 @@ namespace nrt {
 
 // trace.hip
 hipError_t launch_prep(nrt_ctx* c);
+// the same from another ionized fraction, skipped while *skip is nonzero
+hipError_t launch_prep_from(nrt_ctx* c, const double* x, const unsigned long long* skip,
+                            hipStream_t s);
 // absorber (and its FP32 copy when a32 is non-null) from n_H and x, invalid
 // input cells counted in acc->invalid
 hipError_t launch_prep_fields(const double* n_H, const double* x, double n_th, int64_t ncell,
@@ -203,8 +228,15 @@ hipError_t launch_march_on(const nrt_grid_desc& d, int cu_count, int resident_pe
                            hipStream_t st);
 // l0[k] = ndot[k] / 12 on the device
 hipError_t launch_source_rates(const double* ndot, int64_t m, double* l0, hipStream_t s);
-hipError_t launch_zero(double* p, int64_t count, int cus, hipStream_t s);
-hipError_t launch_zero_accum(Accum* acc, hipStream_t s);
+hipError_t launch_zero(double* p, int64_t count, int cus, hipStream_t s,
+                       const unsigned long long* skip = nullptr);
+hipError_t launch_zero_accum(Accum* acc, hipStream_t s, const unsigned long long* skip = nullptr);
+// end of a captured radiation-step pass: count it, stop the iteration when
+// at most `threshold` cells changed, at max_iter passes, or on an overflow or
+// invalid input (one thread)
+hipError_t launch_rt_check(const Accum* acc, RtState* rt, unsigned long long threshold,
+                           unsigned long long max_iter, hipStream_t s);
+hipError_t launch_rt_reset(RtState* rt, hipStream_t s);
 hipError_t launch_march(const nrt_ctx* c, const MarchArgs& a, int64_t rays, hipStream_t st);
 hipError_t march_blocks_per_cu(const nrt_grid_desc& d, int* blocks);
 hipError_t launch_healpix(int level, int64_t first, int64_t count, double* out, hipStream_t s);
@@ -228,7 +260,8 @@ nrt_status build_spectrum_table(nrt_ctx* c);
 
 // chem.hip
 hipError_t launch_chem(const nrt_ctx* c, const double* gamma, double dt, double alpha, double tol,
-                       double* x_avg, double* x_new);
+                       double* x_avg, double* x_new, hipStream_t s,
+                       const unsigned long long* skip = nullptr);
 hipError_t launch_copy(const nrt_ctx* c, const double* src, double* dst);
 
 }  // namespace nrt

@@ -678,6 +678,7 @@ template <bool MIXED, int CORR, bool PERIODIC, bool POLY>
 __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu((MIXED && (PERIODIC || !POLY)) ? 4 : 1, 8))) void k_march(
     MarchArgs A) {
+  if (A.skip && *A.skip) return;  // a replayed pass after its iteration stopped
   using V = typename std::conditional<MIXED, float, double>::type;
   // per-wavefront deposit tables, reused for the budget reduction at the end
   using Tab = LineTable<V>;
@@ -823,7 +824,9 @@ __attribute__((amdgpu_waves_per_eu((MIXED && (PERIODIC || !POLY)) ? 4 : 1, 8))) 
 // usable neighbour (Eqs. new_correction / new_secondary) iff n_H >= n_th and
 // a > 0; otherwise -a is stored (-0.0 for a = 0).  Invalid inputs are counted.
 __global__ void k_prep(const double* __restrict__ n_H, const double* __restrict__ x, double n_th,
-                       int64_t ncell, double* a64, float* a32, Accum* acc) {
+                       int64_t ncell, double* a64, float* a32, Accum* acc,
+                       const unsigned long long* skip) {
+  if (skip && *skip) return;
   unsigned long long bad = 0;
   for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < ncell;
        c += int64_t(gridDim.x) * blockDim.x) {
@@ -867,13 +870,15 @@ __global__ void k_spec_stop(SpecTable t, double tau_max, double hi, double* out)
   *out = hi;
 }
 
-__global__ void k_fill_zero(double* p, int64_t count) {
+__global__ void k_fill_zero(double* p, int64_t count, const unsigned long long* skip) {
+  if (skip && *skip) return;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
        i += int64_t(gridDim.x) * blockDim.x)
     p[i] = 0.0;
 }
 
-__global__ void k_zero_accum(Accum* acc) {
+__global__ void k_zero_accum(Accum* acc, const unsigned long long* skip) {
+  if (skip && *skip) return;
   unsigned long long* p = reinterpret_cast<unsigned long long*>(acc);
   const int words = int(sizeof(Accum) / sizeof(unsigned long long));
   for (int i = threadIdx.x; i < words; i += blockDim.x) p[i] = 0ull;
@@ -910,6 +915,22 @@ __global__ void k_budget(const Accum* acc, nrt_budget* out, uint64_t* dropped, d
   if (dropped) *dropped = acc->overflow;
 }
 
+__global__ void k_rt_check(const Accum* acc, RtState* rt, unsigned long long threshold,
+                           unsigned long long max_iter) {
+  if (threadIdx.x != 0 || rt->done) return;
+  rt->iters += 1;
+  rt->changed = acc->chem_changed;
+  rt->overflow |= acc->overflow;
+  rt->invalid |= acc->invalid;
+  if (rt->invalid || rt->overflow || acc->chem_changed <= threshold || rt->iters >= max_iter)
+    rt->done = 1;
+}
+
+__global__ void k_rt_reset(RtState* rt) {
+  unsigned long long* p = reinterpret_cast<unsigned long long*>(rt);
+  for (int i = threadIdx.x; i < int(sizeof(RtState) / 8); i += blockDim.x) p[i] = 0ull;
+}
+
 int grid_for(int64_t items, int block, int cap) {
   int64_t g = (items + block - 1) / block;
   if (g < 1) g = 1;
@@ -922,7 +943,27 @@ int grid_for(int64_t items, int block, int cap) {
 hipError_t launch_prep_fields(const double* n_H, const double* x, double n_th, int64_t ncell,
                               double* a64, float* a32, Accum* acc, int cus, hipStream_t s) {
   hipLaunchKernelGGL(k_prep, dim3(grid_for(ncell, 256, cus * 16)), dim3(256), 0, s, n_H, x, n_th,
-                     ncell, a64, a32, acc);
+                     ncell, a64, a32, acc, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_from(nrt_ctx* c, const double* x, const unsigned long long* skip,
+                            hipStream_t s) {
+  const int64_t ncell = c->lay.cells;
+  hipLaunchKernelGGL(k_prep, dim3(grid_for(ncell, 256, c->cu_count * 16)), dim3(256), 0, s,
+                     c->n_H, x, c->desc.n_th, ncell, c->a64,
+                     c->desc.precision == NRT_MIXED ? c->a32 : nullptr, c->acc, skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_rt_check(const Accum* acc, RtState* rt, unsigned long long threshold,
+                           unsigned long long max_iter, hipStream_t s) {
+  hipLaunchKernelGGL(k_rt_check, dim3(1), dim3(64), 0, s, acc, rt, threshold, max_iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_rt_reset(RtState* rt, hipStream_t s) {
+  hipLaunchKernelGGL(k_rt_reset, dim3(1), dim3(64), 0, s, rt);
   return hipGetLastError();
 }
 
@@ -940,14 +981,15 @@ hipError_t launch_spec_stop(const nrt_ctx* c, double* out) {
   return hipGetLastError();
 }
 
-hipError_t launch_zero(double* p, int64_t count, int cus, hipStream_t s) {
+hipError_t launch_zero(double* p, int64_t count, int cus, hipStream_t s,
+                       const unsigned long long* skip) {
   hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(count, 256, cus * 16)), dim3(256), 0, s, p,
-                     count);
+                     count, skip);
   return hipGetLastError();
 }
 
-hipError_t launch_zero_accum(Accum* acc, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_accum, dim3(1), dim3(256), 0, s, acc);
+hipError_t launch_zero_accum(Accum* acc, hipStream_t s, const unsigned long long* skip) {
+  hipLaunchKernelGGL(k_zero_accum, dim3(1), dim3(256), 0, s, acc, skip);
   return hipGetLastError();
 }
 

@@ -83,20 +83,24 @@ def run_gpu_replayed(gpu, w, prec, pos=None, ndot=None, merge=False):
 
 
 def test_device_healpix_matches_oracle(gpu, orc):
-    import workloads  # noqa: F401
+    """The march's directions: the table levels (built on the host with the C
+    library's cos and sin) equal the oracle's bit for bit, so the FP64 paths
+    take their decisions on the same directions; levels past the table come
+    from the device's cos and sin, within an ulp of the oracle's."""
     n = 4
-    ctx = gpu.init_grid(gpu.make_desc(n, 1e20), np.ones((n, n, n)), np.zeros((n, n, n)),
-                        device="cuda:0", max_sources=1, ray_capacity=4096)
-    for level in range(0, 7):
+    ctx = gpu.init_grid(gpu.make_desc(n, 1e20, l_max=7), np.ones((n, n, n)),
+                        np.zeros((n, n, n)), device="cuda:0", max_sources=1, ray_capacity=4096)
+    for level in range(0, 8):
         dev = ctx.healpix_dirs(level)
-        ref = orc.healpix_dirs(level)
-        assert np.abs(dev - ref).max() <= 4.5e-16, level
-        # structured values are exact on both sides
-        np.testing.assert_array_equal(dev[ref == 0.0], 0.0)
-        np.testing.assert_array_equal(dev[:, 2], ref[:, 2])
-    last = 12 * 4 ** 14
-    dev = ctx.healpix_dirs(14, last - 64, 64)
-    np.testing.assert_allclose(np.linalg.norm(dev, axis=1), 1.0, atol=1e-15)
+        np.testing.assert_array_equal(dev, orc.healpix_dirs(level), err_msg=str(level))
+    for level in (8, 10, 14):  # past the table: the device function
+        npix = 12 * 4 ** level
+        first = [0, npix // 3, npix - 64]
+        for f in first:
+            dev = ctx.healpix_dirs(level, f, 64)
+            ref = np.array([orc.pix2vec_nest(level, p) for p in range(f, f + 64)])
+            assert np.abs(dev - ref).max() <= 4.5e-16, (level, f)
+            np.testing.assert_array_equal(dev[:, 2], ref[:, 2])  # z is exact on both sides
     ctx.destroy()
 
 
@@ -287,30 +291,42 @@ def test_full_lognormal_128_fp64_and_mixed(gpu, orc):
     np.testing.assert_allclose(g1 + g2, got, rtol=1e-12, atol=1e-13 * got.max())
 
 
-def test_rt_step_stromgren(gpu, orc):
-    """Config 1 (Stromgren Test A): three radiation steps on the GPU against
-    the oracle's, and the radius against the closed form."""
+@pytest.mark.parametrize("prec", [0, 1])
+def test_rt_step_stromgren(gpu, orc, prec):
+    """Config 1 (Stromgren Test A, Table testABCparams): all ten 2 Myr
+    radiation steps on the GPU against the oracle's, in both precisions, and
+    the ionized radius against the closed form (|r_n/r_a - 1| <= 0.10 after
+    steps 1-2, <= 0.05 after steps 3-10).  After the first pass of a step
+    the GPU replays the captured pass (absorber, trace, chemistry and the
+    convergence check on the device)."""
     w = W.config1()
     kw = dict(periodic=False, n_min_ray=w.n_min_ray, l_max=w.l_max, tau_max=w.tau_max,
               n_th=w.n_th)
     alpha = w.extra["alpha_B"] * w.extra["clumping"]
     dt = w.extra["dt_s"]
     p = orc.make_params(w.n, w.h_cm, **kw)
-    ctx = gpu.init_grid(gpu.make_desc(w.n, w.h_cm, **kw), w.n_H, w.x, device="cuda:0",
-                        max_sources=1, ray_capacity=1 << 18)
+    ctx = gpu.init_grid(gpu.make_desc(w.n, w.h_cm, precision=prec, **kw), w.n_H, w.x,
+                        device="cuda:0", max_sources=1, ray_capacity=1 << 18)
     ctx.add_sources(w.pos, w.ndot)
     x_ref = w.x.copy()
     r_s = (3 * w.ndot[0] / (4 * math.pi * alpha * 1e-6)) ** (1 / 3) / w.h_cm
     t_rec = 1 / (alpha * 1e-3)
-    for step in range(1, 4):
+    replayed = 0
+    for step in range(1, 11):
         x_ref, g_ref, b_ref, it_ref = orc.rt_step(p, w.n_H, x_ref, w.pos, w.ndot, dt, alpha)
         g, b, it = ctx.rt_step(dt, alpha)
+        replayed += ctx.last_pass_was_graph()
         x_gpu = ctx.get_ionization().cpu().numpy()
-        assert abs(it - it_ref) <= 1
-        assert np.abs(x_gpu - x_ref).max() <= 1e-6
+        assert abs(it - it_ref) <= 1, (step, it, it_ref)
+        if it == it_ref:
+            assert np.abs(x_gpu - x_ref).max() <= (1e-6 if prec == 0 else 1e-4), step
+        else:  # one pass apart at the threshold: keep the two in step
+            ctx.set_ionization(x_ref)
+            x_gpu = x_ref
         r_n = (3 * x_gpu.sum() / (4 * math.pi)) ** (1 / 3)
         r_a = r_s * (1 - math.exp(-step * dt / t_rec)) ** (1 / 3)
-        assert r_n / r_a == pytest.approx(1.0, abs=0.02)
+        assert r_n / r_a == pytest.approx(1.0, abs=0.10 if step <= 2 else 0.05), step
+    assert replayed >= 5  # most steps take more than one pass
     ctx.destroy()
 
 
@@ -341,6 +357,38 @@ def test_rt_step_convergence_share(gpu, orc):
         else:  # one pass apart near the threshold: keep the two in step
             ctx.set_ionization(x_ref)
     ctx.destroy()
+
+
+def test_rt_step_lognormal_64(gpu, orc):
+    """Radiation steps at 64^3 (lognormal density, 4 sources, periodic):
+    three 0.05 Myr steps that stop once at most 0.1 % of the cells still
+    move, GPU (FP64; mixed) against the oracle's."""
+    n = 64
+    g = np.random.default_rng(64)
+    nH = W.lognormal_density(n, 1e-3, 1.0, g)
+    x = np.zeros((n, n, n))
+    pos = W.uniform_positions(4, n, g)
+    ndot = W.lognormal_values(4, 3e49, 1.0, g)
+    h = 0.3 / (W.SIGMA0 * 1e-3)
+    kw = dict(periodic=True, n_min_ray=4.0, l_max=7, tau_max=30.0, n_th=1e-5)
+    p = orc.make_params(n, h, **kw)
+    dt, alpha = 0.05 * W.MYR_S, W.ALPHA_B_1E4K
+    for prec, tol in ((0, 1e-6), (1, 1e-4)):
+        ctx = gpu.init_grid(gpu.make_desc(n, h, precision=prec, **kw), nH, x, device="cuda:0",
+                            max_sources=4, ray_capacity=1 << 21)
+        ctx.add_sources(pos, ndot)
+        x_ref = x.copy()
+        for step in range(3):
+            x_ref, _, _, it_ref = orc.rt_step(p, nH, x_ref, pos, ndot, dt, alpha,
+                                              conv_frac=1e-3)
+            _, _, it = ctx.rt_step(dt, alpha, conv_frac=1e-3)
+            assert abs(it - it_ref) <= 1, (prec, step, it, it_ref)
+            if it == it_ref:
+                err = np.abs(ctx.get_ionization().cpu().numpy() - x_ref).max()
+                assert err <= tol, (prec, step, err)
+            else:
+                ctx.set_ionization(x_ref)
+        ctx.destroy()
 
 
 @pytest.mark.slow
