@@ -911,16 +911,17 @@ nrt_status nrt_healpix_dirs(nrt_ctx* c, int32_t level, int64_t first, int64_t co
   if (level < 0 || level > NRT_MAX_LEVEL || first < 0 || count < 0 || first + count > npix ||
       (count > 0 && !out))
     return fail(c, NRT_ERR_ARG, "bad HEALPix range");
-  if (size_t(count) * 24 > c->scratch_bytes) return fail(c, NRT_ERR_NOMEM, "range too large");
   if (count == 0) return NRT_OK;
   // levels in the context's table are read from it (the march's values);
-  // deeper levels are computed by the march's device function
+  // deeper levels are computed by the march's device function into scratch
   const double* d = reinterpret_cast<double*>(c->scratch);
-  if (level <= c->lay.dir_levels)
+  if (level <= c->lay.dir_levels) {
     d = c->dirs + 3 * (nrt::dir_table_offset(level) + first);
-  else
+  } else {
+    if (size_t(count) * 24 > c->scratch_bytes) return fail(c, NRT_ERR_NOMEM, "range too large");
     HIP_OR_FAIL(c, nrt::launch_healpix(level, first, count, reinterpret_cast<double*>(c->scratch),
                                        c->stream));
+  }
   HIP_OR_FAIL(c, hipMemcpyAsync(out, d, size_t(count) * 24, hipMemcpyDeviceToHost, c->stream));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   return NRT_OK;
