@@ -74,12 +74,10 @@ void orc_pix2vec_nest(int level, uint64_t pix, double v[3]) {
     s = c;
   } else if (rem < nr) {
     const double ang = (M_PI * (double)rem) / (double)(4 * nr);
-    c = cos(ang);
-    s = sin(ang);
+    sincos(ang, &s, &c); /* the C library's joint sine and cosine */
   } else { /* pi/2 - ang with ang in (0, pi/4) */
     const double ang = (M_PI * (double)(2 * nr - rem)) / (double)(4 * nr);
-    c = sin(ang);
-    s = cos(ang);
+    sincos(ang, &c, &s);
   }
 
   double cx, sy;

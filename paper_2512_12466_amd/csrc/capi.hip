@@ -371,8 +371,8 @@ nrt_status trace_pass(nrt_ctx* c, double* gamma, nrt_budget* out) {
 }
 
 // The direction table of levels 0..c->lay.dir_levels, computed on the host
-// with the C library's cos and sin (the same calls, on the same operations,
-// as a host implementation of the pixelisation makes) and copied once.
+// with the C library's sincos on the pixelisation's correctly rounded
+// geometry, and copied once.
 nrt_status fill_direction_table(nrt_ctx* c) {
   const int64_t total = nrt::dir_table_offset(c->lay.dir_levels + 1);
   std::vector<double> tab;
@@ -388,7 +388,10 @@ nrt_status fill_direction_table(nrt_ctx* c) {
       const int64_t lo = npix * t / nt, hi = npix * (t + 1) / nt;
       for (int64_t p = lo; p < hi; ++p) {
         double* d = tab.data() + 3 * (first + p);
-        nrt::healpix_dir(l, uint32_t(p), d[0], d[1], d[2]);
+        const nrt::HpAngle a = nrt::healpix_angle(l, uint32_t(p));
+        double ca = 1.0, sa = 0.0;
+        if (a.fold >= 2) ::sincos(a.ang, &sa, &ca);
+        nrt::healpix_vector(a, ca, sa, d[0], d[1], d[2]);
       }
     }
   };

@@ -1,8 +1,8 @@
 // HEALPix nested pixel centres (Gorski et al. 2005), the pixelisation along
 // which the paper's rays split (Sec. "Adaptive ray tracing", Fig. raysplit).
-// The same function runs on the host, where the context fills its direction
-// table with the C library's cos and sin, and in the march for levels past
-// the table, with the device's.
+// The geometry is shared by the host, where the context fills its direction
+// table with the C library's sincos, and the march, which evaluates levels
+// past the table with the device's cos and sin.
 //
 // pix = face * Ns^2 + ipf with the in-face coordinates interleaved in ipf
 // (ix on even bits, iy on odd bits); ring jr = (face/4 + 2) Ns - ix - iy - 1;
@@ -28,9 +28,17 @@ __host__ __device__ inline uint32_t hp_compact(uint32_t v) {
   return v;
 }
 
+// Pixel geometry without the trigonometry: z, sin(theta), and the azimuth
+// folded into [0, pi/4] as ang = pi k / (4 nr) with the unfolding rule.
+struct HpAngle {
+  double z, st;
+  double ang;  // folded azimuth (used when fold >= 2)
+  int quad;    // quadrant of the azimuth
+  int fold;    // 0: (c, s) = (1, 0); 1: c = s = sqrt(1/2); 2: (cos, sin) of ang; 3: swapped
+};
+
 // level <= 14, pix < 12 * 4^level: every integer below fits 32 bits
-__host__ __device__ inline void healpix_dir(int level, uint32_t pix, double& dx, double& dy,
-                                            double& dz) {
+__host__ __device__ inline HpAngle healpix_angle(int level, uint32_t pix) {
   const int ns = 1 << level;
   const uint32_t face = pix >> (2 * level);
   const uint32_t ipf = pix - (face << (2 * level));
@@ -39,65 +47,89 @@ __host__ __device__ inline void healpix_dir(int level, uint32_t pix, double& dx,
   const int row = int(face >> 2);  // 0 north, 1 equatorial, 2 south
   const int jr = (row + 2) * ns - ix - iy - 1;
 
+  HpAngle a;
   int nr;
-  double z, st;
   if (jr < ns) {
     nr = jr;
     const double t = double(nr * nr) / double(3 * ns * ns);
-    z = 1.0 - t;
-    st = sqrt(t * (2.0 - t));
+    a.z = 1.0 - t;
+    a.st = sqrt(t * (2.0 - t));
   } else if (jr > 3 * ns) {
     nr = 4 * ns - jr;
     const double t = double(nr * nr) / double(3 * ns * ns);
-    z = t - 1.0;
-    st = sqrt(t * (2.0 - t));
+    a.z = t - 1.0;
+    a.st = sqrt(t * (2.0 - t));
   } else {
     nr = ns;
-    z = double(4 * ns - 2 * jr) / double(3 * ns);
-    st = sqrt((1.0 - z) * (1.0 + z));
+    a.z = double(4 * ns - 2 * jr) / double(3 * ns);
+    a.st = sqrt((1.0 - a.z) * (1.0 + a.z));
   }
 
   const int jpll = 2 * int(face & 3u) + (row == 1 ? 0 : 1);
   int num = jpll * nr + ix - iy;  // phi = (pi/2) num / (2 nr)
   if (num < 0) num += 8 * nr;
   if (num >= 8 * nr) num -= 8 * nr;
-  const int quad = int(num >= 2 * nr) + int(num >= 4 * nr) + int(num >= 6 * nr);
-  const int rem = num - quad * 2 * nr;
-
-  // azimuth within the quadrant folded into [0, pi/4]: one cos and one sin
-  // per lane, swapped for the upper half
-  double c, s;
+  a.quad = int(num >= 2 * nr) + int(num >= 4 * nr) + int(num >= 6 * nr);
+  const int rem = num - a.quad * 2 * nr;
+  // azimuth within the quadrant folded into [0, pi/4]: one cos and one sin,
+  // swapped for the upper half
+  a.ang = 0.0;
   if (rem == 0) {
-    c = 1.0;
-    s = 0.0;
+    a.fold = 0;
   } else if (rem == nr) {
-    c = 0.70710678118654752440;  // sqrt(1/2), correctly rounded
-    s = c;
+    a.fold = 1;
   } else {
     const bool low = rem < nr;
     const int k = low ? rem : 2 * nr - rem;
-    const double ang = (3.14159265358979323846 * double(k)) / double(4 * nr);
-    const double ca = cos(ang), sa = sin(ang);
-    c = low ? ca : sa;
-    s = low ? sa : ca;
+    a.ang = (3.14159265358979323846 * double(k)) / double(4 * nr);
+    a.fold = low ? 2 : 3;
+  }
+  return a;
+}
+
+// The unit vector from the geometry and cos / sin of the folded azimuth.
+__host__ __device__ inline void healpix_vector(const HpAngle& a, double ca, double sa, double& dx,
+                                               double& dy, double& dz) {
+  double c, s;
+  if (a.fold == 0) {
+    c = 1.0;
+    s = 0.0;
+  } else if (a.fold == 1) {
+    c = 0.70710678118654752440;  // sqrt(1/2), correctly rounded
+    s = c;
+  } else {
+    c = a.fold == 2 ? ca : sa;
+    s = a.fold == 2 ? sa : ca;
   }
   double cx, sy;
-  if (quad == 0) {
+  if (a.quad == 0) {
     cx = c;
     sy = s;
-  } else if (quad == 1) {
+  } else if (a.quad == 1) {
     cx = -s;
     sy = c;
-  } else if (quad == 2) {
+  } else if (a.quad == 2) {
     cx = -c;
     sy = -s;
   } else {
     cx = s;
     sy = -c;
   }
-  dx = st * cx;
-  dy = st * sy;
-  dz = z;
+  dx = a.st * cx;
+  dy = a.st * sy;
+  dz = a.z;
+}
+
+// Pixel centre with the device's cos and sin (the march, for levels past
+// the context's direction table).
+__device__ inline void healpix_dir(int level, uint32_t pix, double& dx, double& dy, double& dz) {
+  const HpAngle a = healpix_angle(level, pix);
+  double ca = 1.0, sa = 0.0;
+  if (a.fold >= 2) {
+    ca = cos(a.ang);
+    sa = sin(a.ang);
+  }
+  healpix_vector(a, ca, sa, dx, dy, dz);
 }
 
 }  // namespace nrt
