@@ -392,6 +392,36 @@ def test_rt_step_lognormal_64(gpu, orc):
 
 
 @pytest.mark.slow
+def test_rt_step_bubbles_256_subset(gpu, orc):
+    """A radiation step on the 256^3 bubble field (16 of its 4096 sources,
+    0.1 Myr, stopping once at most 0.1 % of the cells still move), in the
+    benchmark's launch configuration, both precisions against the oracle's
+    step: the same number of passes and the ionized fraction within 1e-6
+    (FP64) / 1e-4 (mixed)."""
+    import bench
+    w = W.config3()
+    s = W.subset(w, 16)
+    kw = dict(periodic=w.periodic, n_min_ray=w.n_min_ray, l_max=w.l_max, tau_max=w.tau_max,
+              n_th=w.n_th)
+    dt, alpha = 0.1 * W.MYR_S, W.ALPHA_B_1E4K
+    x_ref, _, _, it_ref = orc.rt_step(orc.make_params(w.n, w.h_cm, **kw), w.n_H, w.x, s.pos,
+                                      s.ndot, dt, alpha, conv_frac=1e-3)
+    print(f"bubbles-256 rt_step: oracle {it_ref} passes", flush=True)
+    for prec, tol in ((0, 1e-6), (1, 1e-4)):
+        ctx = gpu.init_grid(gpu.make_desc(w.n, w.h_cm, precision=prec, **kw), w.n_H, w.x,
+                            device="cuda:0", max_sources=16, ray_capacity=BENCH_CAPACITY)
+        refill, claim = bench.launch_params(w.name) or (0, 0)
+        ctx.set_tuning(refill_min=refill, claim=claim)
+        ctx.add_sources(s.pos, s.ndot)
+        _, _, it = ctx.rt_step(dt, alpha, conv_frac=1e-3)
+        err = np.abs(ctx.get_ionization().cpu().numpy() - x_ref).max()
+        print(f"bubbles-256 rt_step prec {prec}: {it} passes, max |x - x_oracle| {err:.2e}",
+              flush=True)
+        assert it == it_ref and err <= tol, (prec, it, it_ref, err)
+        ctx.destroy()
+
+
+@pytest.mark.slow
 def test_bubbles_256_4096_sources(gpu, orc):
     """The 256^3 workload with 4096 sources in their own ionized bubbles, at
     full size in the benchmark's launch configuration (replayed device-driven
