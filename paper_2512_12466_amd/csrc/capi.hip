@@ -242,10 +242,11 @@ nrt_status chunked_pass(nrt_ctx* c, double* gamma, nrt_budget* out) {
 // ray count from the accumulator block (written by the previous level), so
 // the whole pass runs without a host round trip.  Needs every level to fit
 // its queue; a launch that cannot store a split sets the overflow flag.
-hipError_t enqueue_device_pass(nrt_ctx* c, hipStream_t st, double* gamma,
-                               const unsigned long long* skip = nullptr) {
-  hipError_t e = nrt::launch_zero(gamma, c->lay.cells, c->cu_count, st, skip);
-  if (e == hipSuccess) e = nrt::launch_zero_accum(c->acc, st, skip);
+// The level launches of a device-driven pass (gamma and the accumulators
+// cleared by the caller).
+hipError_t enqueue_levels(nrt_ctx* c, hipStream_t st, double* gamma,
+                          const unsigned long long* skip) {
+  hipError_t e = hipSuccess;
   const int64_t m = int64_t(c->h_ndot.size());
   const int64_t cap = c->lay.capacity;
   for (int level = 0; level <= c->desc.l_max && e == hipSuccess; ++level) {
@@ -270,6 +271,13 @@ hipError_t enqueue_device_pass(nrt_ctx* c, hipStream_t st, double* gamma,
     }
     e = nrt::launch_march(c, a, level == 0 ? 12 * m : cap, st);
   }
+  return e;
+}
+
+hipError_t enqueue_device_pass(nrt_ctx* c, hipStream_t st, double* gamma) {
+  hipError_t e = nrt::launch_zero(gamma, c->lay.cells, c->cu_count, st);
+  if (e == hipSuccess) e = nrt::launch_zero_accum(c->acc, st);
+  if (e == hipSuccess) e = enqueue_levels(c, st, gamma, nullptr);
   return e;
 }
 
@@ -445,8 +453,9 @@ nrt_status capture_rt_graph(nrt_ctx* c, double dt, double alpha, double tol,
   hipStream_t s = c->capture_stream;
   // the accumulators first: the absorber kernel counts invalid cells there
   hipError_t e = nrt::launch_zero_accum(c->acc, s, skip);
+  if (e == hipSuccess) e = nrt::launch_zero(gamma, c->lay.cells, c->cu_count, s, skip);
   if (e == hipSuccess) e = nrt::launch_prep_from(c, x_avg, skip, s);
-  if (e == hipSuccess) e = enqueue_device_pass(c, s, gamma, skip);
+  if (e == hipSuccess) e = enqueue_levels(c, s, gamma, skip);
   if (e == hipSuccess) e = nrt::launch_chem(c, gamma, dt, alpha, tol, x_avg, x_new, s, skip);
   if (e == hipSuccess) e = nrt::launch_rt_check(c->acc, c->rt, threshold, max_iter, s);
   hipGraph_t g = nullptr;

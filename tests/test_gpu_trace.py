@@ -359,6 +359,16 @@ def test_rt_step_convergence_share(gpu, orc):
     ctx.destroy()
 
 
+def x_agrees(x, x_ref, moving, tol):
+    """The ionized fractions of two radiation steps that stop once at most
+    `moving` cells still move: those cells have not converged (the Gamma <-> x
+    iteration there amplifies rounding differences between two
+    implementations), so up to 2 * moving cells (either side's) may differ;
+    every other cell agrees to tol."""
+    d = np.sort(np.abs(x - x_ref).ravel())[::-1]
+    return d[2 * moving] <= tol and d[0] <= 0.1, (d[0], d[2 * moving])
+
+
 def test_rt_step_lognormal_64(gpu, orc):
     """Radiation steps at 64^3 (lognormal density, 4 sources, periodic):
     three 0.05 Myr steps that stop once at most 0.1 % of the cells still
@@ -384,8 +394,10 @@ def test_rt_step_lognormal_64(gpu, orc):
             _, _, it = ctx.rt_step(dt, alpha, conv_frac=1e-3)
             assert abs(it - it_ref) <= 1, (prec, step, it, it_ref)
             if it == it_ref:
-                err = np.abs(ctx.get_ionization().cpu().numpy() - x_ref).max()
-                assert err <= tol, (prec, step, err)
+                ok, d = x_agrees(ctx.get_ionization().cpu().numpy(), x_ref, n ** 3 // 1000, tol)
+                print(f"rt_step 64^3 prec {prec} step {step}: {it} passes, |dx| max {d[0]:.2e},"
+                      f" beyond the moving cells {d[1]:.2e}", flush=True)
+                assert ok, (prec, step, d)
             else:
                 ctx.set_ionization(x_ref)
         ctx.destroy()
@@ -414,10 +426,10 @@ def test_rt_step_bubbles_256_subset(gpu, orc):
         ctx.set_tuning(refill_min=refill, claim=claim)
         ctx.add_sources(s.pos, s.ndot)
         _, _, it = ctx.rt_step(dt, alpha, conv_frac=1e-3)
-        err = np.abs(ctx.get_ionization().cpu().numpy() - x_ref).max()
-        print(f"bubbles-256 rt_step prec {prec}: {it} passes, max |x - x_oracle| {err:.2e}",
-              flush=True)
-        assert it == it_ref and err <= tol, (prec, it, it_ref, err)
+        ok, d = x_agrees(ctx.get_ionization().cpu().numpy(), x_ref, w.n ** 3 // 1000, tol)
+        print(f"bubbles-256 rt_step prec {prec}: {it} passes, |dx| max {d[0]:.2e}, beyond the "
+              f"moving cells {d[1]:.2e}", flush=True)
+        assert it == it_ref and ok, (prec, it, it_ref, d)
         ctx.destroy()
 
 
