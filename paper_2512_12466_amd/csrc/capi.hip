@@ -558,6 +558,7 @@ MarchArgs march_grid_args(const nrt_grid_desc& d, const double* a64, const float
   a.tau_max = d.tau_max;
   a.s_max = d.periodic ? std::sqrt(3.0) * double(d.n) : INFINITY;
   a.h3 = d.h_cm * d.h_cm * d.h_cm;
+  a.inv_h3 = 1.0 / a.h3;
   a.tau_stop = d.tau_max;
   a.kf = float(d.sigma0 * d.h_cm);
   a.a64 = a64;

@@ -86,6 +86,7 @@ struct MarchArgs {
   int32_t refill_min;    // idle lanes that trigger a refill of a wavefront
   int64_t claim;         // rays a wavefront claims at a time
   double h_cm, sigma0, tau_max, s_max, h3;
+  double inv_h3;     // 1 / h^3 (the mixed path's FP32 deposit scale)
   double r2split;    // split iff s*s > r2split (this level)
   double sqrt_omega; // sqrt of the pixel solid angle (this level)
   double tau_stop;   // the ray stops once tau >= tau_stop: tau_max for a

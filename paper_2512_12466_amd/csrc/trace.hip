@@ -60,11 +60,12 @@ __device__ __forceinline__ int wrap_step(int w, int step, int n) {
   return w;
 }
 
-// parametric distance from the source to the next plane of one axis
+// parametric distance from the source to the next plane of one axis: one
+// division whatever the sign (lanes of a wavefront differ in it), +inf for a
+// zero component
 __device__ __forceinline__ double plane_t(double o, double d, int i) {
-  if (d > 0.0) return (double(i + 1) - o) / d;
-  if (d < 0.0) return (double(i) - o) / d;
-  return __builtin_inf();
+  const double t = (double(d > 0.0 ? i + 1 : i) - o) / d;
+  return d != 0.0 ? t : __builtin_inf();
 }
 
 // start cell of a ray at q = o + s d: floor(q), except that an exact integer
@@ -401,7 +402,7 @@ __device__ int ray_init(RayState& R, Args& A, const Entry& e) {
   const double T = w == 0.0 ? 1.0 : exp(POLY ? -spec_phi(A, w) : -w);
   if (MIXED) {
     R.T = T;
-    R.s_rate = float(R.L / A.h3);
+    R.s_rate = float(R.L * A.inv_h3);
   } else {
     R.P = R.L * T;
   }
