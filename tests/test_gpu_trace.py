@@ -372,7 +372,7 @@ def x_agrees(x, x_ref, moving, tol):
 def test_rt_step_lognormal_64(gpu, orc):
     """Radiation steps at 64^3 (lognormal density, 4 sources, periodic):
     three 0.05 Myr steps that stop once at most 0.1 % of the cells still
-    move, GPU (FP64; mixed) against the oracle's."""
+    move, or after 40 passes, GPU (FP64; mixed) against the oracle's."""
     n = 64
     g = np.random.default_rng(64)
     nH = W.lognormal_density(n, 1e-3, 1.0, g)
@@ -390,8 +390,8 @@ def test_rt_step_lognormal_64(gpu, orc):
         x_ref = x.copy()
         for step in range(3):
             x_ref, _, _, it_ref = orc.rt_step(p, nH, x_ref, pos, ndot, dt, alpha,
-                                              conv_frac=1e-3)
-            _, _, it = ctx.rt_step(dt, alpha, conv_frac=1e-3)
+                                              conv_frac=1e-3, max_iter=40)
+            _, _, it = ctx.rt_step(dt, alpha, conv_frac=1e-3, max_iter=40)
             assert abs(it - it_ref) <= 1, (prec, step, it, it_ref)
             if it == it_ref:
                 ok, d = x_agrees(ctx.get_ionization().cpu().numpy(), x_ref, n ** 3 // 1000, tol)
@@ -641,7 +641,10 @@ def test_late_reion_1024_merged(gpu, orc):
               flush=True)
         tol = 1e-10 if prec == 0 else 1e-4
         assert e_in <= tol and e_out <= tol, (prec, e_in, e_out)
-        assert budget_err(bs, rb) <= (1e-10 if prec == 0 else 1e-6)
+        # the oracle adds this subset's ~5.6e8 per-segment absorptions in one
+        # thread, one after another: its rounding bound is ~n u = 6e-8 of the
+        # total (measured against the GPU's blocked sums: 1.1e-10)
+        assert budget_err(bs, rb) <= (1e-8 if prec == 0 else 1e-6)
         same_counts(bs, rb)
         del got
     (g64, b64), (gmx, bmx) = full[0], full[1]
