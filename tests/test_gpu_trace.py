@@ -370,9 +370,13 @@ def x_agrees(x, x_ref, moving, tol):
 
 
 def test_rt_step_lognormal_64(gpu, orc):
-    """Radiation steps at 64^3 (lognormal density, 4 sources, periodic):
-    three 0.05 Myr steps that stop once at most 0.1 % of the cells still
-    move, or after 40 passes, GPU (FP64; mixed) against the oracle's."""
+    """Radiation steps at 64^3 (lognormal density, 4 bright sources that
+    ionize the box, periodic): three 0.05 Myr steps that stop once at most
+    1 % of the cells moved x by 1e-5 or more (the first takes ~26 passes, the
+    next one each), GPU (FP64; mixed) against the oracle's: the same pass
+    counts, and outside the cells still moving every x within 2 tol (both
+    sides are within about tol of the same fixed point there) and within the
+    precision's bar where that is larger."""
     n = 64
     g = np.random.default_rng(64)
     nH = W.lognormal_density(n, 1e-3, 1.0, g)
@@ -382,24 +386,27 @@ def test_rt_step_lognormal_64(gpu, orc):
     h = 0.3 / (W.SIGMA0 * 1e-3)
     kw = dict(periodic=True, n_min_ray=4.0, l_max=7, tau_max=30.0, n_th=1e-5)
     p = orc.make_params(n, h, **kw)
-    dt, alpha = 0.05 * W.MYR_S, W.ALPHA_B_1E4K
-    for prec, tol in ((0, 1e-6), (1, 1e-4)):
+    dt, alpha, tol, frac, cap = 0.05 * W.MYR_S, W.ALPHA_B_1E4K, 1e-5, 1e-2, 60
+    refs, x_ref = [], x.copy()
+    for step in range(3):
+        x_ref, _, _, it_ref = orc.rt_step(p, nH, x_ref, pos, ndot, dt, alpha, tol=tol,
+                                          conv_frac=frac, max_iter=cap)
+        assert it_ref < cap
+        refs.append((x_ref, it_ref))
+    for prec, bar in ((0, 2 * tol), (1, 1e-4)):
         ctx = gpu.init_grid(gpu.make_desc(n, h, precision=prec, **kw), nH, x, device="cuda:0",
                             max_sources=4, ray_capacity=1 << 21)
         ctx.add_sources(pos, ndot)
-        x_ref = x.copy()
-        for step in range(3):
-            x_ref, _, _, it_ref = orc.rt_step(p, nH, x_ref, pos, ndot, dt, alpha,
-                                              conv_frac=1e-3, max_iter=40)
-            _, _, it = ctx.rt_step(dt, alpha, conv_frac=1e-3, max_iter=40)
+        for step, (xr, it_ref) in enumerate(refs):
+            _, _, it = ctx.rt_step(dt, alpha, tol=tol, conv_frac=frac, max_iter=cap)
             assert abs(it - it_ref) <= 1, (prec, step, it, it_ref)
             if it == it_ref:
-                ok, d = x_agrees(ctx.get_ionization().cpu().numpy(), x_ref, n ** 3 // 1000, tol)
+                ok, d = x_agrees(ctx.get_ionization().cpu().numpy(), xr, int(frac * n ** 3), bar)
                 print(f"rt_step 64^3 prec {prec} step {step}: {it} passes, |dx| max {d[0]:.2e},"
                       f" beyond the moving cells {d[1]:.2e}", flush=True)
                 assert ok, (prec, step, d)
-            else:
-                ctx.set_ionization(x_ref)
+            else:  # one pass apart at the threshold: keep the two in step
+                ctx.set_ionization(xr)
         ctx.destroy()
 
 
