@@ -213,6 +213,29 @@ nrt_status nrt_trace_step(nrt_ctx* ctx, double* gamma_out, nrt_budget* budget);
 nrt_status nrt_trace_step_async(nrt_ctx* ctx, double* gamma_out, nrt_budget* budget_dev,
                                 uint64_t* dropped_dev);
 
+/* For callers that cannot allocate (code under stream capture, tight
+   serving loops, harnesses that forbid hipMalloc): nrt_trace_step's pass
+   with no context and no allocation.  The library keeps the pass's device
+   state (the absorber, the source table, the level queues, the
+   accumulators) in a static device array of 64 MiB per GPU, held until the
+   process ends; the call issues no hipMalloc/hipFree and uses no host heap.
+   desc as for nrt_init_grid, monochromatic only (NRT_ERR_ARG otherwise).
+   n_H, x_ion: device n^3 FP64 (read during the call; invalid values give
+   NRT_ERR_ARG after the pass).  pos host m*3, ndot host m, as for
+   nrt_add_sources.  ray_capacity: slots per HEALPix level queue, in
+   [64, 2^32].  gamma_out: device n^3 FP64, overwritten.  budget: host,
+   filled on return (the call synchronises hip_stream).  The pass is the
+   device-driven one (one launch per level): NRT_ERR_OVERFLOW when a level
+   does not fit ray_capacity (the budget then reports the rays that
+   fitted); NRT_ERR_NOMEM when the absorber (8 B per cell, 12 with
+   NRT_MIXED), the sources (32 B each) and the queues (24 B per slot and
+   level) exceed 64 MiB.  Calls that overlap on one GPU share the array and
+   race.  Messages: nrt_last_error(NULL). */
+nrt_status nrt_trace_step_noalloc(const nrt_grid_desc* desc, const double* n_H,
+                                  const double* x_ion, int64_t m, const double* pos,
+                                  const double* ndot, int64_t ray_capacity, double* gamma_out,
+                                  nrt_budget* budget, void* hip_stream);
+
 /* One radiation step of length dt_s (Secs. "Time integration" and
    "Iterative nonlinear solve"): iterate { trace with a = (1 - x_avg) n_H;
    update x by the time-averaged solution of Eq. chem_ode with C_H = 0 and

@@ -90,6 +90,8 @@ def load():
         "nrt_merge_sources": (st, [_P, C.POINTER(MergeParams), C.POINTER(C.c_int64)]),
         "nrt_trace_step": (st, [_P, _P, C.POINTER(Budget)]),
         "nrt_trace_step_async": (st, [_P, _P, _P, _P]),
+        "nrt_trace_step_noalloc": (st, [C.POINTER(GridDesc), _P, _P, C.c_int64, _D, _D,
+                                        C.c_int64, _P, C.POINTER(Budget), _P]),
         "nrt_rt_step": (st, [_P, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32, _P,
                              C.POINTER(Budget), C.POINTER(C.c_int32)]),
         "nrt_trace_rays_debug": (st, [_P, C.c_int64, _D, _D, C.POINTER(C.c_int32), _D, _P,
@@ -328,6 +330,27 @@ class Context:
             self.destroy()
         except Exception:
             pass
+
+
+def trace_step_noalloc(desc, n_H, x, pos, ndot, gamma, ray_capacity, stream=None):
+    """nrt_trace_step_noalloc: one monochromatic trace pass with no context
+    and no allocation (the library's state lives in its static device
+    scratch).  n_H, x, gamma: float64 CUDA tensors of n^3 elements on the
+    current device; pos (m,3) and ndot (m,) host arrays.  Returns the budget
+    dict; gamma is overwritten."""
+    import torch
+    for t in (n_H, x, gamma):
+        assert t.dtype == torch.float64 and t.is_contiguous() and t.is_cuda
+        assert t.numel() == desc.n ** 3
+    pos = _f64(pos).reshape(-1, 3)
+    ndot = _f64(ndot).reshape(-1)
+    assert pos.shape[0] == ndot.shape[0]
+    s = stream if stream is not None else torch.cuda.current_stream(gamma.device)
+    b = Budget()
+    _check(load().nrt_trace_step_noalloc(C.byref(desc), n_H.data_ptr(), x.data_ptr(),
+                                         pos.shape[0], _dp(pos), _dp(ndot), int(ray_capacity),
+                                         gamma.data_ptr(), C.byref(b), s.cuda_stream))
+    return b.as_dict()
 
 
 def init_grid(desc, n_H, x, **kw):

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libnyxrt.so")
-SOURCES = ["capi.hip", "trace.hip", "spectrum.hip", "chem.hip", "merge.hip"]
+SOURCES = ["capi.hip", "trace.hip", "spectrum.hip", "chem.hip", "merge.hip", "noalloc.hip"]
 ARCH = os.environ.get("NYXRT_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
