@@ -55,7 +55,7 @@ WORKLOADS = {  # name -> generator in workloads/ (configs 1-5 of the method's te
 # smaller workloads, so their pass is one graph replay; the 1024^3 pass is
 # host-driven in chunks of a quarter of a queue, and each chunk launch ends
 # in a tail of long rays, so fewer, larger chunks pay (2^27: 32 GB of queues)
-DEFAULT_CAPACITY = {"late-reion-1024-262144src": 1 << 27}
+DEFAULT_CAPACITY = {"late-reion-1024-262144src": 1 << 29}
 # launch parameters (refill_min, claim) that nrt_autotune picked for these
 # workloads on MI355X, for both paths (for the 1024^3 one, whose passes are
 # too long to autotune, the 128^3 workload's pick, measured better by hand);
