@@ -322,8 +322,9 @@ class Context:
 
     def destroy(self):
         if getattr(self, "_ctx", None):
-            load().nrt_destroy(self._ctx)
+            load().nrt_destroy(self._ctx)  # synchronises the context's stream
             self._ctx = None
+            self.workspace = None  # the device memory is free for the next context
 
     def __del__(self):
         try:
