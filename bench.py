@@ -183,6 +183,8 @@ def run_path(nrt, w, precision, steps, warmup, capacity, graph=0, sources=0, tun
     ev_ms = sorted(a.elapsed_time(z) for a, z in events)
     graph = ctx.last_pass_was_graph()
     ctx.destroy()
+    del ctx
+    torch.cuda.empty_cache()  # the next path's workspace (~160 GB at 1024^3) needs the memory
     return dict(wall_s=wall, steps=done, ms_per_step=1e3 * wall / done,
                 ms_per_step_median_event=ev_ms[len(ev_ms) // 2],
                 segments_per_step=segs // done,

@@ -643,6 +643,8 @@ def test_late_reion_1024_merged(gpu, orc):
         got = gs.cpu().numpy()
         del gs
         ctx.destroy()
+        del ctx
+        torch.cuda.empty_cache()  # each context holds ~160 GB of queues
         e_in, e_out = rel_err(got, ref)
         print(f"late-reion-1024 prec {prec}: subset vs oracle {e_in:.2e} / {e_out:.2e}",
               flush=True)
