@@ -202,10 +202,10 @@ struct LineTable {
 // outcome of a step: keep marching, escaped, truncated, or split
 constexpr int kGoOn = 0, kEscaped = 1, kTruncated = 2, kSplit = 3;
 // cells a busy lane marches per iteration of the wavefront loop (measured on
-// the 128^3 and 1024^3 workloads: 1 -> 3 gains 4-5 %); a cell takes at most
-// 2 new table slots, so a lane's count per iteration fits 4 bits.  The
-// polychromatic march keeps 1 (with 3 its mixed form spills registers).
-constexpr int steps_per_iteration(bool poly) { return poly ? 1 : 3; }
+// the 128^3 and 1024^3 workloads: 1 -> 3 gains 4-5 %, 3 -> 4 about 1 %); a
+// cell takes at most 2 new table slots, so a lane's count per iteration fits
+// 4 bits.  The polychromatic march keeps 1 (with more its mixed form spills).
+constexpr int steps_per_iteration(bool poly) { return poly ? 1 : 4; }
 
 // State of the ray a lane is marching.  Unwrapped cell coordinates (i) keep
 // the plane crossings exact across periodic wraps; wrapped ones (w) address
@@ -611,15 +611,14 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab
   // and recompute its next plane crossing, without diverging on the axis ----
   R.s = tn;
   {
-    // exact masked sums (o and d are finite), which keep the ray state in
-    // registers where a chain of selects over its fields would not
-    const double m0 = ax == 0 ? 1.0 : 0.0, m1 = ax == 1 ? 1.0 : 0.0, m2 = ax == 2 ? 1.0 : 0.0;
-    const int k0 = ax == 0, k1 = ax == 1, k2 = ax == 2;
-    const double o_a = R.o0 * m0 + R.o1 * m1 + R.o2 * m2;
-    const double d_a = R.d0 * m0 + R.d1 * m1 + R.d2 * m2;
+    // the winning axis's fields by two selects each (32-bit selects, cheaper
+    // than masked FP64 sums)
+    const bool a0 = ax == 0, a1 = ax == 1;
+    const double o_a = a0 ? R.o0 : (a1 ? R.o1 : R.o2);
+    const double d_a = a0 ? R.d0 : (a1 ? R.d1 : R.d2);
     const int st_a = d_a > 0.0 ? 1 : -1;
-    const int i_a = R.i0 * k0 + R.i1 * k1 + R.i2 * k2 + st_a;
-    const int w_a = open_box ? i_a : wrap_step(R.w0 * k0 + R.w1 * k1 + R.w2 * k2, st_a, n);
+    const int i_a = (a0 ? R.i0 : (a1 ? R.i1 : R.i2)) + st_a;
+    const int w_a = open_box ? i_a : wrap_step(a0 ? R.w0 : (a1 ? R.w1 : R.w2), st_a, n);
     const double t_a = (double(st_a > 0 ? i_a + 1 : i_a) - o_a) / d_a;
     R.i0 = ax == 0 ? i_a : R.i0;
     R.i1 = ax == 1 ? i_a : R.i1;
@@ -672,7 +671,7 @@ __device__ __forceinline__ void push_pending(unsigned long long* count, const Ra
 // Persistent march: every wavefront takes runs of A.claim rays of the
 // launch's range (its first by position, the rest from a shared counter),
 // refills idle lanes from its run once A.refill_min of them are idle,
-// advances every busy lane by up to 3 cells per iteration, and folds its
+// advances every busy lane by up to 4 cells per iteration, and folds its
 // LDS table into Gamma when half full.  A lane whose ray splits keeps the
 // children's start state in registers; the wavefront appends the children of
 // all pending splits to the next level's queue with one atomicAdd once 32 are
