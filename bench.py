@@ -403,8 +403,11 @@ def summarize_counters(d, out=None):
             agg[key] = (sum(per[i] for i in ids), len(ids))
         return agg
     lf, lw = bench_line("fetch_bench.json"), bench_line("write_bench.json")
-    workload = json.loads([x for x in open(os.path.join(d, "fetch_bench.json"))
-                           if x.startswith("{")][-1])["config"].get("workload", DEFAULT_WORKLOAD)
+    jf = json.loads([x for x in open(os.path.join(d, "fetch_bench.json")) if x.startswith("{")][-1])
+    workload = jf["config"].get("workload", DEFAULT_WORKLOAD)
+    run_args = f"--steps {jf.get('steps', 1)} --warmup {jf.get('warmup', 1)}"
+    if "fp64_path" in jf:
+        run_args += f" --fp64-steps {jf['fp64_path'].get('steps', 1)}"
     out = out or counters_file(workload)
     # the chunking of a host-driven pass follows the order in which children
     # reach the queue, so the launch count may differ by one between runs
@@ -416,7 +419,7 @@ def summarize_counters(d, out=None):
     lines = ["# HBM traffic of k_march from FETCH_SIZE / WRITE_SIZE counter runs",
              "# command (FETCH_SIZE; then WRITE_SIZE with -o write > write_bench.json): "
              "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o fetch -- "
-             f"python3 bench.py --workload {workload} --steps 1 --warmup 2 --no-cpu-baseline "
+             f"python3 bench.py --workload {workload} {run_args} --no-cpu-baseline "
              "--calibrate-copy 1024 > <dir>/fetch_bench.json",
              "# summarized with: python bench.py --summarize-counters <dir>",
              "# bytes per launch: counter KiB x 1024 / copy factor, averaged over the march "
