@@ -29,10 +29,10 @@ sys.path.insert(0, ROOT)
 METRIC = "ray-segments/sec + ms per RT step, FP32-mixed vs FP64, % HBM roofline"
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per segment: absorber of the cell and of its neighbour,
-# read-modify-write of Gamma in both (FP64: 8+8+16+16; mixed: the cell's FP64
-# absorber word, which carries the optical depth of the decisions, the
-# neighbour's FP32 word, FP64 Gamma accumulators: 8+4+16+16)
-BYTES_PER_SEGMENT = {"fp64": 48.0, "mixed": 44.0}
+# read-modify-write of Gamma in both: 8+8+16+16.  Both paths read the one FP64
+# absorber array (the mixed path rounds the neighbour's word to FP32 in
+# registers) and accumulate Gamma in FP64.
+BYTES_PER_SEGMENT = {"fp64": 48.0, "mixed": 48.0}
 DEFAULT_WORKLOAD = "late-reion-1024-262144src"
 # wall-clock budget of a default run (the driver allows 600 s): the FP64 leg
 # and the oracle baseline shrink to fit what the timed mixed passes leave
@@ -398,8 +398,9 @@ def summarize_counters(d, out=None):
         agg = {}
         for key, per in rows.items():
             ids = sorted(per)
-            if key != "copy":
-                ids = ids[-last[key][0]:]
+            # the calibration copies are the run's first three copy
+            # dispatches; later ones (field uploads, readbacks) are not
+            ids = ids[:3] if key == "copy" else ids[-last[key][0]:]
             agg[key] = (sum(per[i] for i in ids), len(ids))
         return agg
     lf, lw = bench_line("fetch_bench.json"), bench_line("write_bench.json")

@@ -52,8 +52,9 @@ typedef enum {
    splits: the optical depth that the tau_max stop reads is accumulated in
    FP64 from the FP64 absorber in both.  NRT_MIXED computes the attenuation,
    the deposits and the correction factors in FP32 (the neighbour's absorber
-   from an FP32 copy) and keeps the transmitted fraction and the photon
-   budget in FP64. */
+   rounded to FP32 where it is read, floored at FLT_MIN) and keeps the
+   transmitted fraction and the photon budget in FP64.  Both paths hold the
+   absorber as one FP64 array, so their workspaces are the same size. */
 typedef enum { NRT_FP64 = 0, NRT_MIXED = 1 } nrt_precision;
 
 /* Overlap correction (Sec. "Geometric correction"). */
@@ -227,9 +228,8 @@ nrt_status nrt_trace_step_async(nrt_ctx* ctx, double* gamma_out, nrt_budget* bud
    filled on return (the call synchronises hip_stream).  The pass is the
    device-driven one (one launch per level): NRT_ERR_OVERFLOW when a level
    does not fit ray_capacity (the budget then reports the rays that
-   fitted); NRT_ERR_NOMEM when the absorber (8 B per cell, 12 with
-   NRT_MIXED), the sources (32 B each) and the queues (24 B per slot and
-   level) exceed 64 MiB.  Calls that overlap on one GPU share the array and
+   fitted); NRT_ERR_NOMEM when the absorber (8 B per cell), the sources
+   (32 B each) and the queues (24 B per slot and level) exceed 64 MiB.  Calls that overlap on one GPU share the array and
    race.  Messages: nrt_last_error(NULL). */
 nrt_status nrt_trace_step_noalloc(const nrt_grid_desc* desc, const double* n_H,
                                   const double* x_ion, int64_t m, const double* pos,

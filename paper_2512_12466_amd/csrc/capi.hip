@@ -114,7 +114,7 @@ nrt_status upload_sources(nrt_ctx* c) {
 }
 
 MarchArgs base_args(const nrt_ctx* c, double* gamma) {
-  MarchArgs a = nrt::march_grid_args(c->desc, c->a64, c->a32, gamma, c->acc);
+  MarchArgs a = nrt::march_grid_args(c->desc, c->a64, gamma, c->acc);
   a.tau_stop = c->desc.spectrum != NRT_SPEC_MONO ? c->spec_tau_stop : c->desc.tau_max;
   a.src_pos = c->src_pos;
   a.src_l0 = c->src_l0;
@@ -545,7 +545,7 @@ const char* check_grid_desc(const nrt_grid_desc* d) { return check_desc(d); }
 
 void set_error(const char* msg) { set_init_error(msg); }
 
-MarchArgs march_grid_args(const nrt_grid_desc& d, const double* a64, const float* a32,
+MarchArgs march_grid_args(const nrt_grid_desc& d, const double* a64,
                           double* gamma, Accum* acc) {
   MarchArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -562,7 +562,6 @@ MarchArgs march_grid_args(const nrt_grid_desc& d, const double* a64, const float
   a.tau_stop = d.tau_max;
   a.kf = float(d.sigma0 * d.h_cm);
   a.a64 = a64;
-  a.a32 = a32;
   a.gamma = gamma;
   a.dir_max_level = -1;  // no direction table: directions computed in the march
   for (int l = 0; l <= kMaxLevel; ++l) {
@@ -587,10 +586,11 @@ Layout plan_layout(const nrt_grid_desc& d, int64_t max_sources, int64_t capacity
   off = align256(off + size_t(cells) * 8);
   L.x = off;
   off = align256(off + size_t(cells) * 8);
-  // FP64 absorber (both paths: the optical depth that carries the tau_max
-  // decision), then its FP32 copy (mixed path only)
+  // FP64 absorber in both paths: the optical depth that carries the tau_max
+  // decision is FP64, and the mixed path rounds the neighbour's absorber to
+  // FP32 where it reads it
   L.a = off;
-  off = align256(off + size_t(cells) * (d.precision == NRT_MIXED ? 12 : 8));
+  off = align256(off + size_t(cells) * 8);
   L.srcpos = off;
   off = align256(off + size_t(max_sources) * 24);
   L.srcl0 = off;
@@ -690,8 +690,6 @@ nrt_status nrt_init_grid(nrt_ctx** out, const nrt_grid_desc* desc, const double*
   c->n_H = reinterpret_cast<double*>(c->ws + L.n_H);
   c->x = reinterpret_cast<double*>(c->ws + L.x);
   c->a64 = reinterpret_cast<double*>(c->ws + L.a);
-  c->a32 = desc->precision == NRT_MIXED ? reinterpret_cast<float*>(c->ws + L.a + size_t(L.cells) * 8)
-                                        : nullptr;
   c->src_pos = reinterpret_cast<double*>(c->ws + L.srcpos);
   c->src_l0 = reinterpret_cast<double*>(c->ws + L.srcl0);
   c->dirs = reinterpret_cast<double*>(c->ws + L.dirs);

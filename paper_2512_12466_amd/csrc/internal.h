@@ -97,7 +97,6 @@ struct MarchArgs {
   const SpecRec64* spec64;      // polychromatic table (FP64 path, and ray set-up)
   const SpecRec32* spec32;      // the same for the mixed path
   const double* a64; // absorber, sign bit set = not a usable neighbour
-  const float* a32;  // its FP32 copy (mixed path: the neighbour's absorber)
   double* gamma;
   // sources
   const double* dirs;     // HEALPix directions (x, y, z) of levels 0..dir_max_level
@@ -145,7 +144,7 @@ Layout plan_layout(const nrt_grid_desc& d, int64_t max_sources, int64_t capacity
 
 // march arguments that follow from the grid alone (no sources, queues or
 // direction table: the caller sets those); tau_stop is tau_max
-MarchArgs march_grid_args(const nrt_grid_desc& d, const double* a64, const float* a32,
+MarchArgs march_grid_args(const nrt_grid_desc& d, const double* a64,
                           double* gamma, Accum* acc);
 
 // the reason a grid descriptor is invalid, or NULL (capi.hip)
@@ -183,7 +182,6 @@ struct nrt_ctx {
   double* n_H;
   double* x;
   double* a64;
-  float* a32;
   double* dirs;
   nrt::SpecRec64* spec64;
   nrt::SpecRec32* spec32;
@@ -219,10 +217,9 @@ hipError_t launch_prep(nrt_ctx* c);
 // the same from another ionized fraction, skipped while *skip is nonzero
 hipError_t launch_prep_from(nrt_ctx* c, const double* x, const unsigned long long* skip,
                             hipStream_t s);
-// absorber (and its FP32 copy when a32 is non-null) from n_H and x, invalid
-// input cells counted in acc->invalid
+// absorber from n_H and x, invalid input cells counted in acc->invalid
 hipError_t launch_prep_fields(const double* n_H, const double* x, double n_th, int64_t ncell,
-                              double* a64, float* a32, Accum* acc, int cus, hipStream_t s);
+                              double* a64, Accum* acc, int cus, hipStream_t s);
 // the march on a persistent grid of at most cu_count * resident_per_cu blocks
 hipError_t launch_march_on(const nrt_grid_desc& d, int cu_count, int resident_per_cu,
                            const nrt_tuning& t, const MarchArgs& a, int64_t rays,

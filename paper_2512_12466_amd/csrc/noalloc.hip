@@ -36,11 +36,10 @@ nrt_status fail(nrt_status s, const char* msg) {
 
 size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Carve-out of the scratch array for a pass: absorber (FP64, then FP32 for
-// the mixed path), source positions and level-0 rates, the accumulators and
-// the level queues 1..l_max.  Returns the bytes used.
+// Carve-out of the scratch array for a pass: FP64 absorber, source positions
+// and level-0 rates, the accumulators and the level queues 1..l_max.
 struct Plan {
-  size_t a64, a32, pos, l0, acc, queues, total;
+  size_t a64, pos, l0, acc, queues, total;
 };
 
 Plan plan(const nrt_grid_desc& d, int64_t m, int64_t capacity) {
@@ -49,8 +48,6 @@ Plan plan(const nrt_grid_desc& d, int64_t m, int64_t capacity) {
   size_t off = 0;
   p.a64 = off;
   off = up256(off + cells * 8);
-  p.a32 = off;
-  if (d.precision == NRT_MIXED) off = up256(off + cells * 4);
   p.pos = off;
   off = up256(off + size_t(m) * 24);
   p.l0 = off;
@@ -125,7 +122,6 @@ nrt_status nrt_trace_step_noalloc(const nrt_grid_desc* desc, const double* n_H,
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const int64_t cells = int64_t(desc->n) * desc->n * desc->n;
   double* a64 = reinterpret_cast<double*>(base + p.a64);
-  float* a32 = desc->precision == NRT_MIXED ? reinterpret_cast<float*>(base + p.a32) : nullptr;
   double* src_pos = reinterpret_cast<double*>(base + p.pos);
   double* src_l0 = reinterpret_cast<double*>(base + p.l0);
   nrt::Accum* acc = reinterpret_cast<nrt::Accum*>(base + p.acc);
@@ -147,7 +143,7 @@ nrt_status nrt_trace_step_noalloc(const nrt_grid_desc* desc, const double* n_H,
   };
   hipError_t e = nrt::launch_zero_accum(acc, s);
   if (e == hipSuccess)
-    e = nrt::launch_prep_fields(n_H, x_ion, desc->n_th, cells, a64, a32, acc, cus, s);
+    e = nrt::launch_prep_fields(n_H, x_ion, desc->n_th, cells, a64, acc, cus, s);
   if (e == hipSuccess && m > 0)
     e = hipMemcpyAsync(src_pos, pos, size_t(m) * 24, hipMemcpyHostToDevice, s);
   // the rates go into their slot as given and are divided by 12 in place on
@@ -162,7 +158,7 @@ nrt_status nrt_trace_step_noalloc(const nrt_grid_desc* desc, const double* n_H,
   // ray count from the count the previous level wrote
   const nrt_tuning t = {0, 0, 0, 0};
   for (int level = 0; level <= desc->l_max && m > 0; ++level) {
-    nrt::MarchArgs a = nrt::march_grid_args(*desc, a64, a32, gamma_out, acc);
+    nrt::MarchArgs a = nrt::march_grid_args(*desc, a64, gamma_out, acc);
     a.src_pos = src_pos;
     a.src_l0 = src_l0;
     a.level = level;

@@ -15,8 +15,8 @@
 // from the FP64 absorber by the same operations, so the two paths march the
 // same segments and split the same rays.  MIXED = true computes the
 // attenuation, the deposits and the correction factors in FP32 (the
-// neighbour's absorber from an FP32 copy) and tracks the transmitted
-// fraction in FP64.  POLY = true integrates the flux
+// neighbour's absorber rounded from its FP64 word) and tracks the
+// transmitted fraction in FP64.  POLY = true integrates the flux
 // over a source spectrum with the table of Phi(tau) = -ln F(tau) built at
 // context set-up (spectrum.hip).  The march is instantiated per precision,
 // correction mode, boundary and spectrum.
@@ -509,10 +509,7 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab
         c2 = cell_index(v0, v1, v2, n);
         neighbour = true;
         cl2 = tab.claim(c2);
-        if (MIXED)
-          raw2_32 = A.a32[c2];
-        else
-          raw2_64 = A.a64[c2];
+        raw2_64 = A.a64[c2];
       }
     }
   }
@@ -576,7 +573,10 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab
   R_t fc = R_t(1);
   bool secondary = false;
   if (near) {
-    const bool usable = neighbour && !(MIXED ? __builtin_signbit(raw2_32) : __builtin_signbit(raw2_64));
+    const bool usable = neighbour && !__builtin_signbit(raw2_64);
+    // the mixed path's FP32 neighbour absorber, floored at the smallest
+    // normal so that its reciprocal stays finite
+    if (MIXED) raw2_32 = fmaxf(float(raw2_64), FLT_MIN);
     R_t f;
     if constexpr (MIXED)
       f = 0.5f + float(dedge) * __builtin_amdgcn_rcpf(float(lpix));
@@ -833,7 +833,7 @@ __attribute__((amdgpu_waves_per_eu((MIXED && (PERIODIC || !POLY)) ? 4 : 1, 8))) 
 // usable neighbour (Eqs. new_correction / new_secondary) iff n_H >= n_th and
 // a > 0; otherwise -a is stored (-0.0 for a = 0).  Invalid inputs are counted.
 __global__ void k_prep(const double* __restrict__ n_H, const double* __restrict__ x, double n_th,
-                       int64_t ncell, double* a64, float* a32, Accum* acc,
+                       int64_t ncell, double* a64, Accum* acc,
                        const unsigned long long* skip) {
   if (skip && *skip) return;
   unsigned long long bad = 0;
@@ -844,11 +844,6 @@ __global__ void k_prep(const double* __restrict__ n_H, const double* __restrict_
     const double a = (1.0 - xx) * nh;
     const bool usable = nh >= n_th && a > 0.0;
     a64[c] = usable ? a : -a;
-    if (a32) {
-      float af = float(a);
-      if (usable && af < FLT_MIN) af = FLT_MIN;
-      a32[c] = usable ? af : -af;
-    }
   }
   if (bad) atomicAdd(&acc->invalid, bad);
 }
@@ -950,9 +945,9 @@ int grid_for(int64_t items, int block, int cap) {
 }  // namespace
 
 hipError_t launch_prep_fields(const double* n_H, const double* x, double n_th, int64_t ncell,
-                              double* a64, float* a32, Accum* acc, int cus, hipStream_t s) {
+                              double* a64, Accum* acc, int cus, hipStream_t s) {
   hipLaunchKernelGGL(k_prep, dim3(grid_for(ncell, 256, cus * 16)), dim3(256), 0, s, n_H, x, n_th,
-                     ncell, a64, a32, acc, nullptr);
+                     ncell, a64, acc, nullptr);
   return hipGetLastError();
 }
 
@@ -960,8 +955,7 @@ hipError_t launch_prep_from(nrt_ctx* c, const double* x, const unsigned long lon
                             hipStream_t s) {
   const int64_t ncell = c->lay.cells;
   hipLaunchKernelGGL(k_prep, dim3(grid_for(ncell, 256, c->cu_count * 16)), dim3(256), 0, s,
-                     c->n_H, x, c->desc.n_th, ncell, c->a64,
-                     c->desc.precision == NRT_MIXED ? c->a32 : nullptr, c->acc, skip);
+                     c->n_H, x, c->desc.n_th, ncell, c->a64, c->acc, skip);
   return hipGetLastError();
 }
 
@@ -977,8 +971,7 @@ hipError_t launch_rt_reset(RtState* rt, hipStream_t s) {
 }
 
 hipError_t launch_prep(nrt_ctx* c) {
-  return launch_prep_fields(c->n_H, c->x, c->desc.n_th, c->lay.cells, c->a64,
-                            c->desc.precision == NRT_MIXED ? c->a32 : nullptr, c->acc,
+  return launch_prep_fields(c->n_H, c->x, c->desc.n_th, c->lay.cells, c->a64, c->acc,
                             c->cu_count, c->stream);
 }
 

@@ -37,9 +37,9 @@ def test_roofline_arithmetic():
     res = dict(segments_per_s_kernel=5e10, avg_launch_ms=2.0, launches=20,
                segments_per_step=10 ** 9, steps=2, graph=True)
     r = bench.roofline("mixed", res, None)
-    assert r["achieved"] == pytest.approx(44 * 5e10 / 1e9)  # 44 B per mixed segment
-    assert r["frac"] == pytest.approx(2200.0 / 8000.0)
-    assert r["algorithmic_bytes_per_launch"] == pytest.approx(44 * 1e9 * 2 / 20)
+    assert r["achieved"] == pytest.approx(48 * 5e10 / 1e9)  # 48 B per mixed segment
+    assert r["frac"] == pytest.approx(2400.0 / 8000.0)
+    assert r["algorithmic_bytes_per_launch"] == pytest.approx(48 * 1e9 * 2 / 20)
     assert r["traffic"] is None and r["mode"] == "graph" and r["bound"] == "hbm"
     f = bench.roofline("fp64", dict(res, graph=False), None)
     assert f["achieved"] == pytest.approx(48 * 5e10 / 1e9) and f["mode"] == "host"
@@ -49,17 +49,19 @@ def test_roofline_arithmetic():
     assert rc["traffic"] == 4e9
     # measured traffic over the launch time against the peak: 4 GB / 2 ms
     assert rc["hbm_frac_measured"] == pytest.approx(2000.0 / 8000.0)
-    assert rc["copy_GBs"] == 5000.0 and rc["frac_of_copy"] == pytest.approx(2200.0 / 5000.0)
+    assert rc["copy_GBs"] == 5000.0 and rc["frac_of_copy"] == pytest.approx(2400.0 / 5000.0)
     assert bench.roofline("mixed", dict(res, graph=False), c)["traffic"] is None
 
 
 def _write_run(d, tag, copy_kib, march_kib, launches):
     """A counter CSV and bench line as rocprofv3 and bench.py write them:
-    three calibration copies, then march dispatches of which the last
-    `launches` belong to the timed step."""
+    three calibration copies, a larger copy, then march dispatches of which
+    the last `launches` belong to the timed step."""
     rows = ["Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value"]
     for i in range(3):
         rows.append(f"{i + 1},__amd_rocclr_copyBuffer,X,{copy_kib}")
+    # a field upload after the calibration: not a calibration copy
+    rows.append(f"4,__amd_rocclr_copyBuffer,X,{100 * copy_kib}")
     for i, v in enumerate(march_kib):
         rows.append(f"{100 + i},\"void nrt::k_march<true, 2, true, false>(nrt::MarchArgs)\",X,{v}")
     open(os.path.join(d, f"{tag}_counter_collection.csv"), "w").write("\n".join(rows) + "\n")
