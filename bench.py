@@ -409,7 +409,18 @@ def summarize_counters(d, out=None):
     run_args = f"--steps {jf.get('steps', 1)} --warmup {jf.get('warmup', 1)}"
     if "fp64_path" in jf:
         run_args += f" --fp64-steps {jf['fp64_path'].get('steps', 1)}"
-    out = out or counters_file(workload)
+    # a spectrum or a source subset is a run of its own: its summary gets its
+    # own name and never stands for the plain workload's
+    name = workload
+    spec = jf["config"].get("spectrum", "mono")
+    if spec != "mono":
+        tag = f"bb{spec['T_K']:g}" if "T_K" in spec else f"pl{spec['alpha']:g}"
+        name += "-" + tag
+        run_args += f" --spectrum {tag[:2]}:{tag[2:]}"
+    if jf["config"].get("subset"):
+        name += f"-{jf['config']['subset']}src-subset"
+        run_args += f" --sources {jf['config']['subset']}"
+    out = out or counters_file(name)
     # the chunking of a host-driven pass follows the order in which children
     # reach the queue, so the launch count may differ by one between runs
     assert {p: m for p, (_, m) in lf.items()} == {p: m for p, (_, m) in lw.items()}, (lf, lw)
@@ -647,6 +658,8 @@ def main():
     if w.merge or args.sources:
         out["config"].update(merge=bool(w.merge), merge_ms=h["merge_ms"],
                              sources_traced=h["sources_traced"])
+    if args.sources:
+        out["config"]["subset"] = args.sources
     if h["tuning"]:
         out["config"]["tuning"] = h["tuning"]
     if err:

@@ -53,7 +53,7 @@ def test_roofline_arithmetic():
     assert bench.roofline("mixed", dict(res, graph=False), c)["traffic"] is None
 
 
-def _write_run(d, tag, copy_kib, march_kib, launches):
+def _write_run(d, tag, copy_kib, march_kib, launches, **config):
     """A counter CSV and bench line as rocprofv3 and bench.py write them:
     three calibration copies, a larger copy, then march dispatches of which
     the last `launches` belong to the timed step."""
@@ -65,7 +65,7 @@ def _write_run(d, tag, copy_kib, march_kib, launches):
     for i, v in enumerate(march_kib):
         rows.append(f"{100 + i},\"void nrt::k_march<true, 2, true, false>(nrt::MarchArgs)\",X,{v}")
     open(os.path.join(d, f"{tag}_counter_collection.csv"), "w").write("\n".join(rows) + "\n")
-    line = {"steps": 1, "config": {"path": "mixed", "workload": "lognormal-128-64src"},
+    line = {"steps": 1, "config": {"path": "mixed", "workload": "lognormal-128-64src", **config},
             "roofline": {"launches": launches, "mode": "graph"}}
     open(os.path.join(d, f"{tag}_bench.json"), "w").write("log line\n" + json.dumps(line) + "\n")
 
@@ -96,6 +96,20 @@ def test_counter_summary_and_staleness(tmp_path, monkeypatch):
     assert bench.read_counters("clustered-512-32768src") is None  # no summary for it
     monkeypatch.setattr(bench, "kernel_hash", lambda: "0" * 16)
     assert bench.read_counters("lognormal-128-64src") is None
+
+
+def test_counter_summary_of_a_spectrum_subset_run(tmp_path, monkeypatch):
+    """A blackbody run on a source subset is summarized under a name of its
+    own, so that it never stands for the plain workload's traffic."""
+    copy_kib = 0.5 * 1024 * 2 ** 20 / 1024
+    cfg = dict(spectrum={"kind": "blackbody", "T_K": 50000.0}, subset=64)
+    _write_run(tmp_path, "fetch", copy_kib, [1.0, 2.0], 1, **cfg)
+    _write_run(tmp_path, "write", 2 * copy_kib, [3.0, 4.0], 1, **cfg)
+    monkeypatch.setattr(bench, "counters_file", lambda w: str(tmp_path / f"k_march_counters_{w}.txt"))
+    bench.summarize_counters(str(tmp_path))
+    out = tmp_path / "k_march_counters_lognormal-128-64src-bb50000-64src-subset.txt"
+    assert "--spectrum bb:50000 --sources 64" in out.read_text()
+    assert not (tmp_path / "k_march_counters_lognormal-128-64src.txt").exists()
 
 
 def test_more_than_one_gpu_exits():
