@@ -61,8 +61,10 @@ DEFAULT_CAPACITY = {"late-reion-1024-262144src": 1 << 29}
 # too long to autotune, the 128^3 workload's pick, measured better by hand);
 # the others keep the library's defaults (16, 128), which it picked for the
 # 256^3 workload.  --tune runs it again, --launch overrides.
-TUNED = {"lognormal-128-64src": (32, 64), "clustered-512-32768src": (16, 256),
-         "late-reion-1024-262144src": (32, 64),
+TUNED = {"lognormal-128-64src": (16, 64), "clustered-512-32768src": (16, 256),
+         # long rays in bubbles: a run is taken and retired whole (refill only
+         # a drained wavefront; measured 74.7 -> 77.0 Gseg/s on a 256-source pass)
+         "late-reion-1024-262144src": (64, 64),
          # a polychromatic pass keeps whole sibling runs alive: refill only a
          # drained wavefront (measured: 64.1 -> 67.9 Gseg/s mixed)
          "lognormal-128-64src+spectrum": (64, 64)}

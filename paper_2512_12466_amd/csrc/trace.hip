@@ -134,8 +134,8 @@ struct LineTable {
   V* val;         // [kLines * kLine] partial sums of the line's cells
   bool on;        // false when line indices do not fit 32 bits below kEmpty
 
-  // First probe for the line of cell c, issued as soon as the cell is known
-  // so that the compare-and-swap is in flight while the step's arithmetic
+  // First probe for the line of cell c, issued ahead of the arithmetic that
+  // precedes the deposit, so that the compare-and-swap is in flight while it
   // runs; `deposit` consumes its result.
   struct Claim {
     uint32_t k, h, old;
@@ -422,21 +422,41 @@ __device__ int ray_init(RayState& R, Args& A, const Entry& e) {
 }
 
 
+// Arguments every step reads, held in scalar registers for the whole
+// launch.  Read from the argument block where they are used, the compiler
+// would reload them there (scalar registers are scarce in the march), and the
+// wait for such a load also waits for every LDS operation in flight.  An
+// empty asm statement makes each value the output of an instruction, which
+// cannot be reloaded, so it stays in a register.
+struct StepConst {
+  double s_max, tau_stop, sigma0;
+  __device__ explicit StepConst(const MarchArgs& A)
+      : s_max(A.s_max), tau_stop(A.tau_stop), sigma0(A.sigma0) {
+    asm volatile("" : "+s"(s_max));
+    asm volatile("" : "+s"(tau_stop));
+    asm volatile("" : "+s"(sigma0));
+  }
+};
+
 // Stop tests at the current cell boundary, then one cell segment: optical
 // depth, Eq. lut_eqn deposit with the overlap correction, advance.  The
 // caller books the photons of a ray that stops.  `inserted` counts new table
 // slots taken by this call's deposits.  Memory latency is hidden by order:
-// the cell's absorber was loaded at the end of the previous step, and the
-// neighbour's is requested before the attenuation arithmetic that follows.
+// the cell's absorber was loaded at the end of the previous step; the
+// neighbour's is requested by every lane (its own cell's when it needs no
+// neighbour), so that the wait for the cell's word leaves that request in
+// flight; the table claims are issued after the attenuation and before the
+// advance, whose arithmetic covers them and the neighbour's load, and the
+// deposits come last.
 template <bool MIXED, int CORR, bool PERIODIC, bool POLY, typename V>
 __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab, LaneAcc& acc,
-                        int& inserted) {
+                        int& inserted, const StepConst& K) {
   const int n = A.n;
   constexpr bool open_box = !PERIODIC;
-  if (PERIODIC && R.s >= A.s_max) return kEscaped;
+  if (PERIODIC && R.s >= K.s_max) return kEscaped;
   // the optical-depth cap (for a spectrum: the threshold optical depth at
   // which the share of photons left falls to e^{-tau_max})
-  if (R.tau >= A.tau_stop) return kTruncated;
+  if (R.tau >= K.tau_stop) return kTruncated;
   // split radius^2 of the launch's level (injected rays never split)
   const double r2s = A.level < 0 ? __builtin_inf() : A.r2split;
   if (R.s * R.s > r2s) return R.level >= A.l_max ? kTruncated : kSplit;
@@ -454,8 +474,6 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab
   double ds = tn - R.s;
   if (ds < 0.0) ds = 0.0;
   const int64_t c = cell_index(R.w0, R.w1, R.w2, n);
-  const auto cl1 = tab.claim(c);
-  typename LineTable<V>::Claim cl2{0u, 0u, 0u};
 
   // ---- overlap geometry (Eqs. correction .. new_secondary): nearest face
   // of the segment midpoint, and the neighbour across it ----
@@ -508,17 +526,20 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab
         const int v2 = fax == 2 ? (open_box ? j2 : wrap_step(R.w2, fdir, n)) : R.w2;
         c2 = cell_index(v0, v1, v2, n);
         neighbour = true;
-        cl2 = tab.claim(c2);
-        raw2_64 = A.a64[c2];
       }
     }
+    // requested by every lane, whether or not it needs a neighbour, so the
+    // load is never skipped by a branch and the wait for this cell's word
+    // below can leave it in flight
+    if constexpr (CORR == NRT_CORR_CONSERVATIVE || CORR == NRT_CORR_NAIVE)
+      raw2_64 = A.a64[neighbour ? c2 : c];
   }
 
   // ---- segment physics (Eq. lut_eqn, Eq. optical_depth) ----
   // the cell's optical depth in FP64, the same operations in both paths
   const double a64 = fabs(R.a64);
   const double dl = ds * A.h_cm;
-  const double dtau64 = A.sigma0 * a64 * dl;
+  const double dtau64 = K.sigma0 * a64 * dl;
   double G64 = 0.0;
   float G32 = 0.0f, a32 = 0.0f;
   if (MIXED) {
@@ -567,6 +588,41 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab
     R.tau += dtau64;
   }
 
+  // ---- table claims, in flight during the advance ----
+  const auto cl1 = tab.claim(c);
+  typename LineTable<V>::Claim cl2{0u, 0u, 0u};
+  if (neighbour) cl2 = tab.claim(c2);
+
+  // ---- advance one cell: step the winning axis (its component is nonzero)
+  // and recompute its next plane crossing, without diverging on the axis ----
+  R.s = tn;
+  {
+    // the winning axis's fields by two selects each (32-bit selects, cheaper
+    // than masked FP64 sums)
+    const bool a0 = ax == 0, a1 = ax == 1;
+    const double o_a = a0 ? R.o0 : (a1 ? R.o1 : R.o2);
+    const double d_a = a0 ? R.d0 : (a1 ? R.d1 : R.d2);
+    const int st_a = d_a > 0.0 ? 1 : -1;
+    const int i_a = (a0 ? R.i0 : (a1 ? R.i1 : R.i2)) + st_a;
+    const int w_a = open_box ? i_a : wrap_step(a0 ? R.w0 : (a1 ? R.w1 : R.w2), st_a, n);
+    const double t_a = (double(st_a > 0 ? i_a + 1 : i_a) - o_a) / d_a;
+    R.i0 = ax == 0 ? i_a : R.i0;
+    R.i1 = ax == 1 ? i_a : R.i1;
+    R.i2 = ax == 2 ? i_a : R.i2;
+    R.w0 = ax == 0 ? w_a : R.w0;
+    R.w1 = ax == 1 ? w_a : R.w1;
+    R.w2 = ax == 2 ? w_a : R.w2;
+    R.t0 = ax == 0 ? t_a : R.t0;
+    R.t1 = ax == 1 ? t_a : R.t1;
+    R.t2 = ax == 2 ? t_a : R.t2;
+  }
+  acc.segments += 1;
+  const bool escaped = open_box &&
+      (R.i0 < 0 || R.i0 >= n || R.i1 < 0 || R.i1 >= n || R.i2 < 0 || R.i2 >= n);
+  // absorber of the next cell, consumed by the next step (a ray that left
+  // the open box reads its last cell's instead)
+  R.a64 = A.a64[escaped ? c : cell_index(R.w0, R.w1, R.w2, n)];
+
   // ---- overlap correction values (the decision above is FP64; the factor
   // is FP32 in the mixed path) ----
   using R_t = typename std::conditional<MIXED, float, double>::type;
@@ -607,36 +663,7 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab
     if (secondary) inserted += tab.deposit(cl2, c2, ((1.0 - fc) * (a64 / raw2_64)) * G64);
   }
 
-  // ---- advance one cell: step the winning axis (its component is nonzero)
-  // and recompute its next plane crossing, without diverging on the axis ----
-  R.s = tn;
-  {
-    // the winning axis's fields by two selects each (32-bit selects, cheaper
-    // than masked FP64 sums)
-    const bool a0 = ax == 0, a1 = ax == 1;
-    const double o_a = a0 ? R.o0 : (a1 ? R.o1 : R.o2);
-    const double d_a = a0 ? R.d0 : (a1 ? R.d1 : R.d2);
-    const int st_a = d_a > 0.0 ? 1 : -1;
-    const int i_a = (a0 ? R.i0 : (a1 ? R.i1 : R.i2)) + st_a;
-    const int w_a = open_box ? i_a : wrap_step(a0 ? R.w0 : (a1 ? R.w1 : R.w2), st_a, n);
-    const double t_a = (double(st_a > 0 ? i_a + 1 : i_a) - o_a) / d_a;
-    R.i0 = ax == 0 ? i_a : R.i0;
-    R.i1 = ax == 1 ? i_a : R.i1;
-    R.i2 = ax == 2 ? i_a : R.i2;
-    R.w0 = ax == 0 ? w_a : R.w0;
-    R.w1 = ax == 1 ? w_a : R.w1;
-    R.w2 = ax == 2 ? w_a : R.w2;
-    R.t0 = ax == 0 ? t_a : R.t0;
-    R.t1 = ax == 1 ? t_a : R.t1;
-    R.t2 = ax == 2 ? t_a : R.t2;
-  }
-  acc.segments += 1;
-  if (open_box &&
-      (R.i0 < 0 || R.i0 >= n || R.i1 < 0 || R.i1 >= n || R.i2 < 0 || R.i2 >= n))
-    return kEscaped;
-  // absorber of the next cell, consumed by the next step
-  R.a64 = A.a64[cell_index(R.w0, R.w1, R.w2, n)];
-  return kGoOn;
+  return escaped ? kEscaped : kGoOn;
 }
 
 // Whole wavefront: append the four children of every lane with a pending
@@ -724,6 +751,7 @@ __attribute__((amdgpu_waves_per_eu((MIXED && (PERIODIC || !POLY)) ? 4 : 1, 8))) 
   int64_t pool_end = pool + claim < total ? pool + claim : total;
   bool exhausted = pool >= total;
   if (exhausted) pool = pool_end = 0;
+  const StepConst K(A);
   int fill = 0;                    // wavefront-uniform occupied line slots
   for (;;) {
     const uint64_t idle = __ballot(!busy);
@@ -762,7 +790,7 @@ __attribute__((amdgpu_waves_per_eu((MIXED && (PERIODIC || !POLY)) ? 4 : 1, 8))) 
     int code = kGoOn, inserted = 0;
 #pragma unroll 1
     for (int k = 0; k < steps_per_iteration(POLY) && busy; ++k) {
-      code = ray_step<MIXED, CORR, PERIODIC, POLY>(R, A, tab, acc, inserted);
+      code = ray_step<MIXED, CORR, PERIODIC, POLY>(R, A, tab, acc, inserted, K);
       if (code != kGoOn) {
         busy = false;
         const double carried = MIXED ? R.L * R.T : R.P;

@@ -27,7 +27,7 @@ def test_parse_spectrum():
 
 
 def test_launch_params():
-    assert bench.launch_params("lognormal-128-64src") == (32, 64)
+    assert bench.launch_params("lognormal-128-64src") == (16, 64)
     assert bench.launch_params("lognormal-128-64src", 1) == (64, 64)
     assert bench.launch_params("clustered-512-32768src", 1) == (16, 256)
     assert bench.launch_params("lognormal-256-4096src-bubbles") is None
