@@ -469,11 +469,13 @@ def host_cpu():
 
 
 # oracle baseline sample per workload: sources of the (unmerged) catalogue,
-# sized for 10-30 s of oracle work (the oracle keeps a private FP64 Gamma
-# per thread within 16 GB, so at 1024^3 it runs one thread, and a source of
-# the late-reionization field casts about 3e8 segments)
+# sized for 10-30 s of oracle work.  The oracle keeps a private FP64 Gamma per
+# thread (8.6 GB at 1024^3), held within 80 GB of host memory, and it splits
+# its work by source, so at 1024^3 it takes 8 sources on 8 threads (a source
+# of the late-reionization field casts about 5e8 segments, 20 s on one core).
 CPU_SOURCES = {"lognormal-128-64src": 64, "lognormal-256-4096src-bubbles": 64,
-               "clustered-512-32768src": 64, "late-reion-1024-262144src": 1}
+               "clustered-512-32768src": 64, "late-reion-1024-262144src": 8}
+CPU_GAMMA_BYTES = 80e9
 
 
 def cpu_baseline(w, sources, spectrum=(0, 0.0)):
@@ -483,9 +485,10 @@ def cpu_baseline(w, sources, spectrum=(0, 0.0)):
     import oracle
     import workloads as W
     nproc, share, model = host_cpu()
-    # the oracle's own caps: the CPU share, 16, the sources, 16 GB of Gamma
+    # the oracle's own caps: the CPU share, 16, the sources, and the host
+    # memory of its per-thread Gamma
     threads = max(1, min(16, share, len(w.ndot) if sources <= 0 else sources,
-                         int(16e9 / (8.0 * w.n ** 3))))
+                         int(CPU_GAMMA_BYTES / (8.0 * w.n ** 3))))
     s = W.subset(w, sources)
     p = oracle.make_params(w.n, w.h_cm, periodic=w.periodic, n_min_ray=w.n_min_ray,
                            l_max=w.l_max, tau_max=w.tau_max, n_th=w.n_th,

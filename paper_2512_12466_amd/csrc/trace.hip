@@ -202,10 +202,11 @@ struct LineTable {
 // outcome of a step: keep marching, escaped, truncated, or split
 constexpr int kGoOn = 0, kEscaped = 1, kTruncated = 2, kSplit = 3;
 // cells a busy lane marches per iteration of the wavefront loop (measured on
-// the 128^3 and 1024^3 workloads: 1 -> 3 gains 4-5 %, 3 -> 4 about 1 %); a
-// cell takes at most 2 new table slots, so a lane's count per iteration fits
-// 4 bits.  The polychromatic march keeps 1 (with more its mixed form spills).
-constexpr int steps_per_iteration(bool poly) { return poly ? 1 : 4; }
+// the 128^3, 512^3 and 1024^3 workloads: 1 -> 3 gains 4-5 %, 3 -> 4 about
+// 1 %, 4 -> 8 another 0.5-3 %); a cell takes at most 2 new table slots, so a
+// lane's count per iteration fits 5 bits.  The polychromatic march keeps 1
+// (with more its mixed form spills).
+constexpr int steps_per_iteration(bool poly) { return poly ? 1 : 8; }
 
 // State of the ray a lane is marching.  Unwrapped cell coordinates (i) keep
 // the plane crossings exact across periodic wraps; wrapped ones (w) address
@@ -698,7 +699,7 @@ __device__ __forceinline__ void push_pending(unsigned long long* count, const Ra
 // Persistent march: every wavefront takes runs of A.claim rays of the
 // launch's range (its first by position, the rest from a shared counter),
 // refills idle lanes from its run once A.refill_min of them are idle,
-// advances every busy lane by up to 4 cells per iteration, and folds its
+// advances every busy lane by up to 8 cells per iteration, and folds its
 // LDS table into Gamma when half full.  A lane whose ray splits keeps the
 // children's start state in registers; the wavefront appends the children of
 // all pending splits to the next level's queue with one atomicAdd once 32 are
@@ -799,7 +800,8 @@ __attribute__((amdgpu_waves_per_eu((MIXED && (PERIODIC || !POLY)) ? 4 : 1, 8))) 
       }
     }
     fill += __popcll(__ballot(inserted & 1)) + 2 * __popcll(__ballot(inserted & 2)) +
-            4 * __popcll(__ballot(inserted & 4)) + 8 * __popcll(__ballot(inserted & 8));
+            4 * __popcll(__ballot(inserted & 4)) + 8 * __popcll(__ballot(inserted & 8)) +
+            16 * __popcll(__ballot(inserted & 16));
     const bool splits = code == kSplit;
     if (__ballot(splits && pend)) {  // a lane splits again
       ArgsK& F = fresh_args();
