@@ -488,44 +488,42 @@ __device__ int ray_step(RayState& R, const MarchArgs& A, const LineTable<V>& tab
     const double rm = 0.5 * (R.s + tn);
     // sqrt of the pixel solid angle: sqrt(Omega(0)) 2^-level, exactly
     lpix = rm * ldexp(A.sqrt_omega_tab[0], -R.level);
-    int fax = 0, fdir;
-    {
-      const double m0 = R.o0 + rm * R.d0;
-      const double dm = m0 - double(R.i0), dp = double(R.i0 + 1) - m0;
-      dedge = dm < dp ? dm : dp;
-      fdir = dm < dp ? -1 : (dp < dm ? 1 : (R.d0 < 0.0 ? -1 : 1));
-    }
-    {
-      const double m1 = R.o1 + rm * R.d1;
-      const double dm = m1 - double(R.i1), dp = double(R.i1 + 1) - m1;
-      const double da = dm < dp ? dm : dp;
-      if (da < dedge) {
-        dedge = da;
-        fax = 1;
-        fdir = dm < dp ? -1 : (dp < dm ? 1 : (R.d1 < 0.0 ? -1 : 1));
-      }
-    }
-    {
-      const double m2 = R.o2 + rm * R.d2;
-      const double dm = m2 - double(R.i2), dp = double(R.i2 + 1) - m2;
-      const double da = dm < dp ? dm : dp;
-      if (da < dedge) {
-        dedge = da;
-        fax = 2;
-        fdir = dm < dp ? -1 : (dp < dm ? 1 : (R.d2 < 0.0 ? -1 : 1));
-      }
-    }
+    // per axis: distance to the nearer face and its side (-1 lower, +1
+    // upper; an exact tie goes the way the ray points); the first axis wins
+    // ties between axes.  Selects only, no branches.
+    const double m0 = R.o0 + rm * R.d0;
+    const double dm0 = m0 - double(R.i0), dp0 = double(R.i0 + 1) - m0;
+    const double m1 = R.o1 + rm * R.d1;
+    const double dm1 = m1 - double(R.i1), dp1 = double(R.i1 + 1) - m1;
+    const double m2 = R.o2 + rm * R.d2;
+    const double dm2 = m2 - double(R.i2), dp2 = double(R.i2 + 1) - m2;
+    // both comparisons up front, so that the side is two selects
+    const bool lt0 = dm0 < dp0, gt0 = dp0 < dm0;
+    const bool lt1 = dm1 < dp1, gt1 = dp1 < dm1;
+    const bool lt2 = dm2 < dp2, gt2 = dp2 < dm2;
+    const int s0 = lt0 ? -1 : (gt0 ? 1 : (R.d0 < 0.0 ? -1 : 1));
+    const int s1 = lt1 ? -1 : (gt1 ? 1 : (R.d1 < 0.0 ? -1 : 1));
+    const int s2 = lt2 ? -1 : (gt2 ? 1 : (R.d2 < 0.0 ? -1 : 1));
+    const double da0 = lt0 ? dm0 : dp0;
+    const double da1 = lt1 ? dm1 : dp1;
+    const double da2 = lt2 ? dm2 : dp2;
+    const bool b1 = da1 < da0;
+    const double d01 = b1 ? da1 : da0;
+    const bool b2 = da2 < d01;
+    dedge = b2 ? da2 : d01;
+    const int fax = b2 ? 2 : (b1 ? 1 : 0);
+    const int fdir = b2 ? s2 : (b1 ? s1 : s0);
     near = dedge < 0.5 * lpix;
     if (near && (CORR == NRT_CORR_CONSERVATIVE || CORR == NRT_CORR_NAIVE)) {
-      const int j0 = R.i0 + (fax == 0 ? fdir : 0);
-      const int j1 = R.i1 + (fax == 1 ? fdir : 0);
-      const int j2 = R.i2 + (fax == 2 ? fdir : 0);
-      const bool j_out = j0 < 0 || j0 >= n || j1 < 0 || j1 >= n || j2 < 0 || j2 >= n;
-      if (!open_box || !j_out) {
-        const int v0 = fax == 0 ? (open_box ? j0 : wrap_step(R.w0, fdir, n)) : R.w0;
-        const int v1 = fax == 1 ? (open_box ? j1 : wrap_step(R.w1, fdir, n)) : R.w1;
-        const int v2 = fax == 2 ? (open_box ? j2 : wrap_step(R.w2, fdir, n)) : R.w2;
-        c2 = cell_index(v0, v1, v2, n);
+      // the neighbour differs from the cell in the face's axis only
+      const int i_f = fax == 0 ? R.i0 : (fax == 1 ? R.i1 : R.i2);
+      const int j_f = i_f + fdir;
+      if (!open_box || !(j_f < 0 || j_f >= n)) {
+        const int w_f = open_box ? i_f : (fax == 0 ? R.w0 : (fax == 1 ? R.w1 : R.w2));
+        const int v_f = open_box ? j_f : wrap_step(w_f, fdir, n);
+        // n^2 <= 2^24 fits 32 bits: one 32 x 32 -> 64 signed multiply
+        const int32_t stride = fax == 0 ? 1 : (fax == 1 ? n : n * n);
+        c2 = c + int64_t(v_f - w_f) * int64_t(stride);
         neighbour = true;
       }
     }
