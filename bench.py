@@ -34,9 +34,10 @@ HBM_PEAK_GBS = 8000.0
 # registers) and accumulate Gamma in FP64.
 BYTES_PER_SEGMENT = {"fp64": 48.0, "mixed": 48.0}
 DEFAULT_WORKLOAD = "late-reion-1024-262144src"
-# wall-clock budget of a default run (the driver allows 600 s): the FP64 leg
-# and the oracle baseline shrink to fit what the timed mixed passes leave
-RUN_BUDGET_S = 450.0
+# wall-clock budget of a default run's GPU legs (the whole run must end within
+# 600 s): the FP64 leg takes as many passes as the timed mixed passes leave,
+# and the oracle baseline (about 30 s at 1024^3) follows
+RUN_BUDGET_S = 420.0
 T_START = time.perf_counter()
 
 
@@ -469,12 +470,13 @@ def host_cpu():
 
 
 # oracle baseline sample per workload: sources of the (unmerged) catalogue,
-# sized for 10-30 s of oracle work.  The oracle keeps a private FP64 Gamma per
-# thread (8.6 GB at 1024^3), held within 80 GB of host memory, and it splits
-# its work by source, so at 1024^3 it takes 8 sources on 8 threads (a source
-# of the late-reionization field casts about 5e8 segments, 20 s on one core).
+# sized for 10-30 s of oracle work.  The oracle splits its work by source and
+# keeps a private FP64 Gamma per thread (8.6 GB at 1024^3, held within 80 GB
+# of host memory), which it allocates, clears and reduces on top of the trace:
+# at 1024^3, 8 sources on 8 threads took 66 s for 2.0e9 segments (one source
+# on one thread: 20 s for 5.4e8), so the 1024^3 sample is 2 sources.
 CPU_SOURCES = {"lognormal-128-64src": 64, "lognormal-256-4096src-bubbles": 64,
-               "clustered-512-32768src": 64, "late-reion-1024-262144src": 8}
+               "clustered-512-32768src": 64, "late-reion-1024-262144src": 2}
 CPU_GAMMA_BYTES = 80e9
 
 

@@ -1,5 +1,5 @@
 /*
- * Sanitizer driver for the oracle -- TEST INFRASTRUCTURE ONLY.
+ * Sanitizer test program for the oracle -- TEST INFRASTRUCTURE ONLY.
  *
  * Built twice by tests/test_oracle_sanitizers.py with gcc (never for a GPU):
  * with AddressSanitizer + UndefinedBehaviorSanitizer, and with

@@ -1,6 +1,6 @@
 """The oracle under host sanitizers: AddressSanitizer with
 UndefinedBehaviorSanitizer, and ThreadSanitizer for the threaded trace
-(private Gamma per thread, shared source counter under a mutex).  The driver
+(private Gamma per thread, shared source counter under a mutex).  The test program
 (oracle/sanitize_main.c) runs every oracle entry point on small inputs and
 checks each trace's photon budget; any sanitizer report fails the run."""
 import os
