@@ -203,10 +203,10 @@ struct LineTable {
 constexpr int kGoOn = 0, kEscaped = 1, kTruncated = 2, kSplit = 3;
 // cells a busy lane marches per iteration of the wavefront loop (measured on
 // the 128^3, 512^3 and 1024^3 workloads: 1 -> 3 gains 4-5 %, 3 -> 4 about
-// 1 %, 4 -> 8 another 0.5-3 %); a cell takes at most 2 new table slots, so a
-// lane's count per iteration fits 5 bits.  The polychromatic march keeps 1
-// (with more its mixed form spills).
-constexpr int steps_per_iteration(bool poly) { return poly ? 1 : 8; }
+// 1 %, 4 -> 8 another 0.5-3 %; the polychromatic march 1 -> 8 gains 5-11 %);
+// a cell takes at most 2 new table slots, so a lane's count per iteration
+// fits 5 bits
+constexpr int kCellsPerIteration = 8;
 
 // State of the ray a lane is marching.  Unwrapped cell coordinates (i) keep
 // the plane crossings exact across periodic wraps; wrapped ones (w) address
@@ -702,10 +702,10 @@ __device__ __forceinline__ void push_pending(unsigned long long* count, const Ra
 // children's start state in registers; the wavefront appends the children of
 // all pending splits to the next level's queue with one atomicAdd once 32 are
 // pending (or a pending lane splits again, or the run ends).
-// The periodic mixed polychromatic march is held to 128 VGPRs (it fits with
-// no spills), which keeps 4 waves per SIMD as its LDS allows; every other
-// instantiation (the open-box ones would spill under the same cap) is left
-// to the compiler.
+// The mixed march is held to 128 VGPRs, which keeps 4 waves per SIMD as its
+// LDS allows (it fits with no VGPR spills), except the open-box
+// polychromatic one, which would spill under that cap; it and the FP64
+// march are left to the compiler (3 waves per SIMD).
 template <bool MIXED, int CORR, bool PERIODIC, bool POLY>
 __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu((MIXED && (PERIODIC || !POLY)) ? 4 : 1, 8))) void k_march(
@@ -788,7 +788,7 @@ __attribute__((amdgpu_waves_per_eu((MIXED && (PERIODIC || !POLY)) ? 4 : 1, 8))) 
     // split pushes, table occupancy); a lane that stops sits out the rest
     int code = kGoOn, inserted = 0;
 #pragma unroll 1
-    for (int k = 0; k < steps_per_iteration(POLY) && busy; ++k) {
+    for (int k = 0; k < kCellsPerIteration && busy; ++k) {
       code = ray_step<MIXED, CORR, PERIODIC, POLY>(R, A, tab, acc, inserted, K);
       if (code != kGoOn) {
         busy = false;
